@@ -1,0 +1,265 @@
+"""Benchmark of the SELL-C-sigma spMVM on one MI355X.
+
+One step is one FP64 SELL-C-sigma spMVM y = A x on the 27-point stencil over
+a 160^3 grid (n = 4,096,000, 109,215,352 nonzeros; values U[0.5,1.5), x
+U[-1,1)), the regular, bandwidth-bound workload. The timed region holds K
+back-to-back products with matrix, x and y resident in device memory,
+bracketed by device synchronisations and timed with HIP events on the stream
+the kernels run on. GF/s counts the useful 2 * nnz flops per product.
+
+Printed as one JSON line, with
+  roofline: algorithmic bytes of one product (padded matrix at 12 B per slot,
+            x and y once, chunk metadata) over the measured time per product,
+            against the 8 TB/s HBM peak; traffic = HBM bytes per product from
+            the hardware counters recorded under profiles/ when the kernel
+            sources are unchanged since, else null;
+  cpu_baseline: the CPU oracle (CRS, double, OpenMP over rows) on the same
+            matrix on the host cores;
+  forms:    FP32 / BF16 value storage, the block form (k right-hand sides) on
+            the power-law n = 1,000,000 matrix, the batched launch over 64
+            power-law matrices, and the power-law n = 2,000,000 matrix;
+  probes:   read-only and copy bandwidth (the paper's roofline b).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spMVM GF/s + HBM GB/s vs 8 TB/s roofline; FP64 plain vs block-k/FP32/BF16"
+PEAK_HBM_GBS = 8000.0
+HEADLINE = dict(workload="stencil27_160", C=32, sigma=1)
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources: the stored counter traffic is valid only for
+    the kernels it was measured on."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1307_6209_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(src_hash: str):
+    p = os.path.join(ROOT, "profiles", "traffic_stencil27_160_fp64.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def to_dev(A):
+    import torch
+    return (torch.from_numpy(A.rpt).cuda(), torch.from_numpy(A.col).cuda(), torch.from_numpy(A.val).cuda())
+
+
+def time_calls(fn, steps: int, warmup: int):
+    """Average seconds per call of fn over `steps` calls after `warmup`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def cpu_baseline(A, x, budget_s: float = 10.0) -> dict:
+    """The oracle's CRS product on the host cores (OpenMP over rows)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    sched = oracle.schedule_for(A)
+    t0 = time.perf_counter()
+    oracle.crs_spmv(A, x, nthreads=threads, sched=sched)
+    t1 = time.perf_counter() - t0
+    reps = int(max(3, min(500, budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.crs_spmv(A, x, nthreads=threads, sched=sched)
+    t = (time.perf_counter() - t0) / reps
+    return {"value": round(2.0 * A.nnz / t * 1e-9, 3), "unit": "GF/s", "cores": threads, "kind": "oracle",
+            "sample": "full %s matrix (%d nonzeros), CRS product in double, %d repetitions, OpenMP %s" % (
+                A.name, A.nnz, reps, "static" if sched == 0 else "guided,1")}
+
+
+def run_forms(args) -> dict:
+    import torch
+    import numpy as np
+    import synth
+    from paper_1307_6209_amd import sellcs
+    out = {}
+    # block form on the power-law n = 1,000,000 matrix
+    A = synth.workload("powerlaw_1m")
+    r, c, v = to_dev(A)
+    h = sellcs.sell_build(r, c, v, A.ncols, 32, 1024)
+    spmmv = {}
+    for k in (1, 4, 8, 16, 32):
+        X = torch.from_numpy(synth.block_vector(A.ncols, k)).cuda()
+        Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
+        t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
+        spmmv["k%d" % k] = round(2.0 * A.nnz * k / t * 1e-9, 2)
+    out["spmmv_powerlaw_1m_gfs"] = spmmv
+    h.close()
+    del r, c, v
+    # 64 uneven power-law matrices in one persistent launch
+    mats = synth.batch_workload(64)
+    hs = []
+    for i, B in enumerate(mats):
+        rr, cc, vv = to_dev(B)
+        hs.append(sellcs.sell_build(rr, cc, vv, B.ncols, 32, 1024))
+    b = sellcs.sell_batch_create(hs)
+    xs = [torch.from_numpy(synth.uniform(B.ncols, 5 + i)).cuda() for i, B in enumerate(mats)]
+    ys = [torch.empty(B.nrows, dtype=torch.float64, device="cuda") for B in mats]
+    nnz = sum(B.nnz for B in mats)
+    t = time_calls(lambda: sellcs.sell_batch_spmv(b, xs, ys), max(10, args.steps // 10), 3)
+    out["batch64_gfs"] = round(2.0 * nnz / t * 1e-9, 2)
+    out["batch64_us"] = round(t * 1e6, 2)
+    t_seq = time_calls(lambda: [sellcs.sell_spmv(hh, xx, yy) for hh, xx, yy in zip(hs, xs, ys)],
+                       max(5, args.steps // 50), 2)
+    out["batch64_separate_launches_us"] = round(t_seq * 1e6, 2)
+    b.close()
+    for hh in hs:
+        hh.close()
+    # power-law n = 2,000,000: plain and globally sorted
+    A = synth.workload("powerlaw_2m")
+    r, c, v = to_dev(A)
+    x = torch.from_numpy(synth.uniform(A.ncols)).cuda()
+    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    pl = {}
+    for C, s in ((32, 1), (32, 2**14), (32, A.nrows), (16, A.nrows)):
+        h = sellcs.sell_build(r, c, v, A.ncols, C, s)
+        t = time_calls(lambda: sellcs.sell_spmv(h, x, y), max(20, args.steps // 5), 5)
+        pl["C%d_sigma%d" % (C, s)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(h.info["beta"], 4)}
+        h.close()
+    out["powerlaw_2m"] = pl
+    return out
+
+
+def model_report(model, b_read, gfs, achieved, inf, A, sizes, traffic) -> dict:
+    """The code-balance model (Sect. 4) with the measured read bandwidth as b:
+    balance at the ideal alpha = 1/N_nzc, the resulting bound, and alpha
+    solved from the counter traffic when it is available."""
+    nnzr = A.nnz / A.nrows
+    bal = model.general_balance(1.0 / nnzr, inf["beta"], nnzr, inf["C"], 1, sizes)
+    p_model = b_read / bal
+    rep = {"b_read_gbs": b_read, "frac_of_b_read": round(achieved / b_read, 4),
+           "balance_ideal_alpha_bytes_per_flop": round(bal, 4), "P_model_gfs": round(p_model, 1),
+           "frac_of_model": round(gfs / p_model, 4), "P_bar_paper_gfs": round(model.best_attainable(b_read, inf["beta"]), 1)}
+    if traffic:
+        rep["alpha_measured"] = round(model.general_alpha_from_volume(traffic, A.nnz, inf["beta"], nnzr, inf["C"], 1,
+                                                                      sizes), 5)
+        rep["alpha_ideal"] = round(1.0 / nnzr, 5)
+    return rep
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-forms", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="short run for hardware counters: a few products and one copy probe")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the SELL-C-sigma product here is a single-device kernel "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1307_6209_amd import model, sellcs
+
+    torch.cuda.set_device(0)
+    A = synth.workload(HEADLINE["workload"])
+    x_np = synth.uniform(A.ncols, synth.SEED_X + 2)
+    r, c, v = to_dev(A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = sellcs.sell_build(r, c, v, A.ncols, HEADLINE["C"], HEADLINE["sigma"])
+    build_s = time.perf_counter() - t0
+    inf = h.info
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+
+    if args.pmc_pass:
+        for _ in range(5):
+            sellcs.sell_spmv(h, x, y)
+        torch.cuda.synchronize()
+        sellcs.sell_probe_bandwidth(1, 1 << 30, 1)  # copy of 512 MiB -> 512 MiB: the counter calibration
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_pass": True, "padded": inf["padded"]}))
+        return
+
+    probes = {"read_gbs": round(sellcs.sell_probe_bandwidth(0, 4 << 30, 10), 1),
+              "copy_gbs": round(sellcs.sell_probe_bandwidth(1, 4 << 30, 10), 1)}
+
+    sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup)
+    gfs = 2.0 * A.nnz / sec * 1e-9
+    sizes = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1)
+    alg = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes)
+    achieved = alg / sec * 1e-9
+    src_hash = kernel_source_hash()
+    traffic = stored_traffic(src_hash)
+    nnzr = A.nnz / A.nrows
+    line = {
+        "metric": METRIC,
+        "value": round(gfs, 2),
+        "unit": "GF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "stencil27_160 (27-point stencil, 160^3 grid)", "n": A.nrows, "nnz": A.nnz,
+                   "format": "SELL-%d-%d" % (HEADLINE["C"], HEADLINE["sigma"]), "beta": round(inf["beta"], 6),
+                   "padded_slots": inf["padded"], "index": "int32", "values": "f64", "x": "f64", "y": "f64"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg},
+        "model": model_report(model, probes["read_gbs"], gfs, achieved, inf, A, sizes, traffic),
+        "build_ms": round(build_s * 1e3, 2),
+        "probes": probes,
+        "kernel_source_hash": src_hash,
+    }
+    # precision forms on the same matrix
+    forms = {}
+    for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
+        hf = sellcs.sell_build(r, c, v, A.ncols, HEADLINE["C"], HEADLINE["sigma"], val_dtype=vd, acc_dtype=ad)
+        xf = x.float()
+        yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
+        t = time_calls(lambda: sellcs.sell_spmv(hf, xf, yf), max(50, args.steps // 4), 10)
+        forms["%s_val_%s_acc" % (vd, ad)] = round(2.0 * A.nnz / t * 1e-9, 2)
+        hf.close()
+    line["forms_stencil27_160_gfs"] = forms
+    h.close()
+    del r, c, v
+    if not args.no_forms:
+        line["forms"] = run_forms(args)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(A, x_np)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * sellcs.h -- C ABI of the SELL-C-sigma sparse matrix-vector library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kreutzer, Hager, Wellein, Fehske, Bishop, "A unified sparse matrix
+ * data format for efficient general sparse matrix-vector multiply on modern
+ * processors with wide SIMD units" (arXiv:1307.6209).
+ *
+ * Conventions for every entry point
+ *   - Pointers named "device" refer to GPU memory of the current HIP device;
+ *     "host" pointers refer to CPU memory. Sizes are element counts unless
+ *     stated otherwise.
+ *   - A stream argument is a hipStream_t passed as void*; NULL is the null
+ *     stream. Calls documented as asynchronous only enqueue work on it.
+ *   - Every call returns a sell_status. Nothing is printed and nothing is
+ *     thrown across the ABI. On failure, sell_last_error() returns a
+ *     thread-local message with the detail (for SELL_ERR_HIP: the HIP error
+ *     string). Faults inside kernels surface at the caller's next
+ *     synchronisation, as for any HIP call.
+ *   - Index types: row pointers int64, column indices int32, chunk offsets
+ *     int64, permutation and chunk widths int32. nrows and ncols must be
+ *     below 2^31.
+ */
+#ifndef SELLCS_H
+#define SELLCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SELL_OK = 0,
+  SELL_ERR_INVALID_ARG = 1, /* null pointer, negative size, k < 1, ... */
+  SELL_ERR_BAD_CRS = 2,     /* malformed CRS input (see sell_build) */
+  SELL_ERR_OOM = 3,         /* device (or allocator callback) allocation failed */
+  SELL_ERR_UNSUPPORTED = 4, /* C, dtype combination or size outside what the kernels take */
+  SELL_ERR_HIP = 5          /* a HIP runtime call failed; text in sell_last_error() */
+} sell_status;
+
+typedef enum { SELL_F64 = 0, SELL_F32 = 1, SELL_BF16 = 2 } sell_dtype;
+
+typedef struct sell_matrix *sell_handle;
+typedef struct sell_batch_s *sell_batch;
+
+/* Optional device allocator. alloc returns NULL on failure (reported as
+ * SELL_ERR_OOM). When absent the library uses hipMalloc/hipFree. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} sell_allocator;
+
+/* A general sparse matrix in CRS form (Sect. 3.1 of the paper): row i holds
+ * val[rpt[i] .. rpt[i+1]-1] at columns col[rpt[i] .. rpt[i+1]-1]. All three
+ * arrays are device pointers, borrowed for the duration of sell_build only.
+ * Columns need not be sorted; repeated (row, column) pairs are kept as
+ * separate terms. */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int64_t *rpt; /* device, nrows + 1 */
+  const int32_t *col; /* device, nnz */
+  const double *val;  /* device, nnz */
+} sell_crs;
+
+/* Build options; a zeroed struct (or NULL) selects FP64 values, FP64
+ * accumulation and automatic kernel parameters. */
+typedef struct {
+  sell_dtype val_dtype; /* storage of the matrix values: F64, F32 or BF16 */
+  sell_dtype acc_dtype; /* accumulation and y: F64 or F32 (F64 values need F64) */
+  int32_t unroll;       /* chunk columns in flight per lane: 0 auto, else 4 or 8 */
+  int32_t seg_steps;    /* longest run of wave steps one work unit covers before a
+                           chunk is split across waves: 0 auto, < 0 never split */
+  int32_t ktile;        /* right-hand sides per pass in sell_spmmv: 0 auto, else a
+                           power of two <= 64 */
+  int32_t kmax;         /* largest k sell_spmmv will be called with on matrices
+                           whose chunks are split (sizes the partial-sum buffer):
+                           0 means 32 */
+  const sell_allocator *alloc; /* NULL: hipMalloc/hipFree */
+} sell_build_opts;
+
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  int32_t C;             /* chunk height */
+  int64_t sigma;         /* sorting scope as requested */
+  int64_t nchunks;       /* N_c = ceil(nrows / C) */
+  int64_t padded;        /* stored slots cs[N_c] = sum_i C * cl[i] */
+  double beta;           /* chunk occupancy nnz / padded (1 when padded == 0) */
+  double zeta;           /* coefficient of variation of the row lengths */
+  int64_t max_row_len;
+  sell_dtype val_dtype, x_dtype, acc_dtype;
+  int32_t lanes_per_row; /* lanes of one wavefront that share a row (64 / C, or 1) */
+  int32_t unroll;
+  int32_t seg_steps;     /* split threshold in wave steps */
+  int64_t nunits;        /* work units of one sell_spmv launch */
+  int64_t nsplit;        /* row slices whose chunk is split over several waves */
+  int32_t has_perm;      /* 0 when the row order is the identity (sigma == 1) */
+  int64_t device_bytes;  /* device memory held by the handle */
+} sell_info_t;
+
+/*
+ * sell_build -- convert CRS to SELL-C-sigma on the device (Sects. 3.3, 3.4).
+ *
+ * Rows are sorted by descending length within windows of sigma consecutive
+ * rows (ties keep the original order; sigma = 1 keeps the original order,
+ * sigma >= nrows sorts globally). Rows are then grouped into chunks of C,
+ * each chunk padded to its longest row (padding: value 0, column 0) and
+ * stored column by column; chunk i starts at cs[i] and is cl[i] columns wide
+ * (Eqs. (nc), (max); Listing "SELL-4-sigma spMVM kernel" for the layout
+ * val[cs[i] + j*C + r]). Column indices stay the caller's, so x and y keep
+ * the original numbering; y is written through the permutation.
+ *
+ * A:      CRS input, device arrays (borrowed).
+ * C:      1, 2, 4, 8, 16, 32, 64 or 128; otherwise SELL_ERR_UNSUPPORTED.
+ * sigma:  >= 1; otherwise SELL_ERR_INVALID_ARG.
+ * opts:   NULL for defaults. Supported (val, acc) pairs: (F64, F64),
+ *         (F32, F32), (F32, F64), (BF16, F32), (BF16, F64); x is F64 for F64
+ *         values and F32 otherwise. Values are rounded to nearest-even.
+ * stream: all device work runs on it; the call synchronises it once to read
+ *         the padded size and the validation flags.
+ * out:    receives the new handle; it owns every device array it holds.
+ * Errors: SELL_ERR_BAD_CRS when rpt[0] != 0, rpt decreases, rpt[nrows] !=
+ *         nnz, a row is longer than 2^31 - 1, or a column lies outside
+ *         [0, ncols). SELL_ERR_OOM on allocation failure. No handle is
+ *         returned on failure.
+ */
+sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma,
+                       const sell_build_opts *opts, void *stream,
+                       sell_handle *out);
+
+/*
+ * sell_spmv -- y = A x (Sect. 3.3, Listing "SELL-4-sigma spMVM kernel"),
+ * asynchronous on stream.
+ *
+ * x: device, ncols elements of the handle's x dtype (F64 or F32).
+ * y: device, nrows elements of the accumulation dtype; fully overwritten,
+ *    never read. x must not overlap y.
+ * Padding slots multiply x[0] by zero, so x must be finite.
+ * Calls on one handle must not overlap in time (they share the handle's
+ * partial-sum buffer for split chunks): order them on one stream or
+ * synchronise between streams.
+ */
+sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream);
+
+/*
+ * sell_spmmv -- Y = A X for k right-hand sides at once, asynchronous.
+ * (Block form; the paper treats k = 1 only. Column v of Y equals sell_spmv
+ * applied to column v of X.) FP64 handles only.
+ *
+ * X: device, row-major ncols x k (X[c*k + v]); Y: device, row-major
+ * nrows x k, fully overwritten. k >= 1; on handles with split chunks k must
+ * not exceed the kmax given at build. Same overlap rule as sell_spmv.
+ */
+sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t k,
+                       void *stream);
+
+/* sell_info -- host copy of the handle's sizes and parameters. */
+sell_status sell_info(sell_handle h, sell_info_t *info);
+
+/*
+ * sell_export -- copy the device arrays to host buffers (synchronous).
+ * perm: nrows int32 (perm[p] = original row at sorted position p; identity
+ * when sigma == 1); cl: nchunks int32; cs: nchunks + 1 int64; col: padded
+ * int32; val: padded elements of the value dtype (bfloat16 as raw uint16).
+ * Any pointer may be NULL to skip that array.
+ */
+sell_status sell_export(sell_handle h, int32_t *perm, int32_t *cl, int64_t *cs,
+                        int32_t *col, void *val);
+
+/* sell_destroy -- release the handle and its device memory (synchronises
+ * the device first). NULL is accepted. */
+sell_status sell_destroy(sell_handle h);
+
+/*
+ * sell_batch_create -- prepare one persistent launch that multiplies count
+ * matrices with their own vectors. All handles must share C and dtypes;
+ * they are borrowed and must outlive the batch. The work of all matrices
+ * (chunk slices, long chunks split) is divided into equal-cost slices, one
+ * per resident wavefront, and the launch is captured once in a hipGraph.
+ */
+sell_status sell_batch_create(const sell_handle *hs, int32_t count,
+                              sell_batch *out);
+
+/*
+ * sell_batch_spmv -- ys[b] = A_b xs[b] for every matrix of the batch, as one
+ * graph launch on stream (asynchronous). xs and ys are host arrays of count
+ * device pointers. When they differ from the previous call, the device copy
+ * of the pointer table is rewritten first (this synchronises the stream).
+ */
+sell_status sell_batch_spmv(sell_batch b, const void *const *xs,
+                            void *const *ys, void *stream);
+
+sell_status sell_batch_destroy(sell_batch b);
+
+/* Autotuner search space (zero-length lists fall back to defaults). */
+typedef struct {
+  const int32_t *C;       int32_t nC;       /* chunk heights */
+  const int64_t *sigma;   int32_t nsigma;   /* sorting scopes */
+  const int32_t *unroll;  int32_t nunroll;
+  const int32_t *ktile;   int32_t nktile;   /* used when k > 1 */
+  sell_dtype val_dtype, acc_dtype;
+  int32_t reps;           /* timed repetitions per candidate (0: 20) */
+} sell_tune_space;
+
+typedef struct {
+  int32_t C;
+  int64_t sigma;
+  int32_t unroll;
+  int32_t ktile;
+  double gflops;        /* useful 2 * nnz * k flops per second / 1e9 */
+  double us_per_call;
+  double beta;
+  int32_t candidates;   /* configurations measured */
+} sell_tuned;
+
+/*
+ * sell_autotune -- build and time every configuration of the search space on
+ * A (device CRS, borrowed) with k right-hand sides and return the fastest by
+ * useful GF/s. Synchronous on stream; uses temporary device memory.
+ */
+sell_status sell_autotune(const sell_crs *A, int32_t k,
+                          const sell_tune_space *space, void *stream,
+                          sell_tuned *best);
+
+/*
+ * sell_probe_bandwidth -- achievable device memory bandwidth b of the
+ * roofline model (Sect. 2.1): kind 0 streams bytes through a read-only sum
+ * (the "reduction" benchmark), kind 1 copies bytes/2 to another bytes/2
+ * buffer (the "copy" benchmark; no write-allocate factor on this device).
+ * Runs reps timed passes after one warm-up on stream; *gbs receives the mean
+ * bandwidth in GB/s (1e9 bytes). Allocates and frees its own buffers.
+ */
+sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps,
+                                 void *stream, double *gbs);
+
+const char *sell_status_string(sell_status s);
+const char *sell_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SELLCS_H */

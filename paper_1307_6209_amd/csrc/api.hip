@@ -1,0 +1,818 @@
+// Host side of the SELL-C-sigma library: argument checking, device memory,
+// the construction pipeline, work planning for long chunks, the batched
+// persistent launch with its hipGraph, the autotuner and the probes.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "sell_internal.h"
+
+using sell::Geom;
+
+namespace {
+
+thread_local std::string g_err;
+
+sell_status fail(sell_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+sell_status hip_fail(const char *what, hipError_t e) {
+  return fail(SELL_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SELL_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(#call, e_);    \
+  } while (0)
+
+int combo_of(sell_dtype v, sell_dtype a) {
+  if (v == SELL_F64 && a == SELL_F64) return sell::COMBO_F64_F64;
+  if (v == SELL_F32 && a == SELL_F32) return sell::COMBO_F32_F32;
+  if (v == SELL_F32 && a == SELL_F64) return sell::COMBO_F32_F64;
+  if (v == SELL_BF16 && a == SELL_F32) return sell::COMBO_BF16_F32;
+  if (v == SELL_BF16 && a == SELL_F64) return sell::COMBO_BF16_F64;
+  return -1;
+}
+
+size_t dtype_size(sell_dtype d) { return d == SELL_F64 ? 8 : d == SELL_F32 ? 4 : 2; }
+
+bool valid_C(int C) { return C >= 1 && C <= 128 && (C & (C - 1)) == 0; }
+
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+struct DeviceInfo {
+  int cus = 256;
+};
+
+DeviceInfo device_info() {
+  DeviceInfo d;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) d.cus = v;
+  }
+  return d;
+}
+
+// Device memory through the caller's allocator or hipMalloc.
+struct Mem {
+  sell_allocator alloc{};
+  bool custom = false;
+  void *get(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (custom) {
+      p = alloc.alloc(bytes, alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    return p;
+  }
+  void put(void *p) {
+    if (!p) return;
+    if (custom) alloc.free(p, alloc.ctx);
+    else (void)hipFree(p);
+  }
+};
+
+// Temporary device buffers released at scope exit.
+struct Temp {
+  Mem mem;
+  std::vector<void *> ptrs;
+  explicit Temp(const Mem &m) : mem(m) {}
+  void *get(size_t bytes) {
+    void *p = mem.get(bytes);
+    if (p) ptrs.push_back(p);
+    return p;
+  }
+  ~Temp() {
+    for (void *p : ptrs) mem.put(p);
+  }
+};
+
+void *owned_alloc(sell_matrix *h, const Mem &mem, size_t bytes) {
+  Mem m = mem;
+  void *p = m.get(bytes);
+  if (p) {
+    h->owned.push_back({p, bytes});
+    h->device_bytes += (int64_t)(bytes ? bytes : 256);
+  }
+  return p;
+}
+
+void free_owned(sell_matrix *h) {
+  Mem m;
+  m.alloc = h->alloc;
+  m.custom = h->custom_alloc;
+  for (auto &pr : h->owned) m.put(pr.first);
+  h->owned.clear();
+}
+
+// Split plan of one matrix for a given segment length (in wave steps).
+struct ItemSteps {
+  std::vector<int32_t> steps;  // per item
+  int64_t total = 0;
+  int32_t max = 0;
+};
+
+ItemSteps item_steps(const std::vector<int32_t> &cl, const Geom &g) {
+  ItemSteps r;
+  r.steps.resize(cl.size() * (size_t)g.wpc);
+  for (size_t c = 0; c < cl.size(); ++c) {
+    int32_t st = (cl[c] + g.T - 1) / g.T;
+    for (int h = 0; h < g.wpc; ++h) r.steps[c * g.wpc + h] = st;
+    r.total += (int64_t)st * g.wpc;
+    r.max = std::max(r.max, st);
+  }
+  return r;
+}
+
+// Automatic segment length: long enough that a unit amortises its fixed
+// cost, short enough that no unit is much longer than an average wave's
+// share of the whole product (resident waves: CUs x 32).
+int32_t auto_seg_steps(int64_t total_steps, int cus) {
+  int64_t resident = (int64_t)cus * 32;
+  int64_t s = total_steps / (2 * resident);
+  if (s < 64) s = 64;
+  if (s > (1 << 20)) s = 1 << 20;
+  return (int32_t)s;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Construction
+// ===========================================================================
+extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, const sell_build_opts *opts,
+                                  void *stream, sell_handle *out) {
+  if (!A || !out) return fail(SELL_ERR_INVALID_ARG, "sell_build: null argument");
+  *out = nullptr;
+  if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0) return fail(SELL_ERR_INVALID_ARG, "sell_build: negative size");
+  if (A->nrows >= (int64_t)1 << 31 || A->ncols >= (int64_t)1 << 31)
+    return fail(SELL_ERR_UNSUPPORTED, "sell_build: nrows and ncols must be below 2^31");
+  if (!A->rpt || (A->nnz > 0 && (!A->col || !A->val)))
+    return fail(SELL_ERR_INVALID_ARG, "sell_build: null CRS array");
+  if (!valid_C(C)) return fail(SELL_ERR_UNSUPPORTED, "sell_build: C must be a power of two in [1, 128]");
+  if (sigma < 1) return fail(SELL_ERR_INVALID_ARG, "sell_build: sigma must be >= 1");
+  sell_build_opts o{};
+  if (opts) o = *opts;
+  else {
+    o.val_dtype = SELL_F64;
+    o.acc_dtype = SELL_F64;
+  }
+  const int combo = combo_of(o.val_dtype, o.acc_dtype);
+  if (combo < 0) return fail(SELL_ERR_UNSUPPORTED, "sell_build: unsupported (value, accumulation) dtype pair");
+  if (o.unroll != 0 && o.unroll != 4 && o.unroll != 8)
+    return fail(SELL_ERR_UNSUPPORTED, "sell_build: unroll must be 0, 4 or 8");
+  if (o.ktile < 0 || o.ktile > 64 || (o.ktile & (o.ktile - 1)) != 0)
+    return fail(SELL_ERR_UNSUPPORTED, "sell_build: ktile must be 0 or a power of two <= 64");
+  if (o.kmax < 0) return fail(SELL_ERR_INVALID_ARG, "sell_build: kmax must be >= 0");
+  if (o.alloc && (!o.alloc->alloc || !o.alloc->free))
+    return fail(SELL_ERR_INVALID_ARG, "sell_build: allocator needs alloc and free");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::unique_ptr<sell_matrix> h(new sell_matrix());
+  h->nrows = A->nrows;
+  h->ncols = A->ncols;
+  h->nnz = A->nnz;
+  h->C = C;
+  h->sigma = sigma;
+  h->g = sell::geom_of(C);
+  h->vdt = o.val_dtype;
+  h->adt = o.acc_dtype;
+  h->xdt = o.val_dtype == SELL_F64 ? SELL_F64 : SELL_F32;
+  h->combo = combo;
+  h->unroll = o.unroll ? o.unroll : 8;
+  h->ktile = o.ktile;
+  h->kmax = o.kmax ? o.kmax : 32;
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  Mem mem;
+  if (o.alloc) {
+    mem.alloc = *o.alloc;
+    mem.custom = true;
+    h->alloc = *o.alloc;
+    h->custom_alloc = true;
+  }
+  struct Guard {
+    sell_matrix *h;
+    bool armed = true;
+    ~Guard() {
+      if (armed && h) free_owned(h);
+    }
+  } guard{h.get()};
+
+  const int64_t n = A->nrows;
+  const int64_t nc = (n + C - 1) / C;
+  h->nchunks = nc;
+  Temp tmp(mem);
+
+  // small counters: flags (u32), maxlen (i32), sumsq (u64)
+  struct Small {
+    uint32_t flags;
+    int32_t maxlen;
+    unsigned long long sumsq;
+    int64_t padded;
+  };
+  Small *dsmall = static_cast<Small *>(tmp.get(sizeof(Small)));
+  int32_t *len = static_cast<int32_t *>(tmp.get(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1)));
+  if (!dsmall || !len) return fail(SELL_ERR_OOM, "sell_build: temporary allocation failed");
+  SELL_HIP(hipMemsetAsync(dsmall, 0, sizeof(Small), s));
+  SELL_HIP(sell::build_rowlen(A->rpt, n, A->nnz, len, &dsmall->flags, &dsmall->sumsq, &dsmall->maxlen, s));
+  SELL_HIP(sell::build_colcheck(A->col, A->nnz, A->ncols, &dsmall->flags, s));
+
+  // sigma-window sort
+  int64_t sig = std::min<int64_t>(sigma, std::max<int64_t>(n, 1));
+  if (sig > 1 && n > 1) {
+    h->perm = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * (size_t)n));
+    uint64_t *ka = nullptr, *kb = nullptr;
+    if (sig > 4096) {
+      ka = static_cast<uint64_t *>(tmp.get(sizeof(uint64_t) * (size_t)n));
+      kb = static_cast<uint64_t *>(tmp.get(sizeof(uint64_t) * (size_t)n));
+      if (!ka || !kb) return fail(SELL_ERR_OOM, "sell_build: sort buffers");
+    }
+    if (!h->perm) return fail(SELL_ERR_OOM, "sell_build: perm");
+    SELL_HIP(sell::build_sort(len, n, sig, ka, kb, h->perm, s));
+  }
+
+  // chunk widths and offsets
+  h->cl = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * (size_t)std::max<int64_t>(nc, 1)));
+  h->cs = static_cast<int64_t *>(owned_alloc(h.get(), mem, sizeof(int64_t) * (size_t)(nc + 1)));
+  int64_t *scan_tmp = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)sell::scan_tmp_elems(nc + 1)));
+  if (!h->cl || !h->cs || !scan_tmp) return fail(SELL_ERR_OOM, "sell_build: chunk arrays");
+  SELL_HIP(sell::build_chunkwidth(len, h->perm, n, C, nc, h->cl, h->cs, s));
+  SELL_HIP(sell::build_scan(h->cs, h->cs, nc + 1, scan_tmp, s));
+  SELL_HIP(hipMemcpyAsync(&dsmall->padded, h->cs + nc, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  Small hs{};
+  SELL_HIP(hipMemcpyAsync(&hs, dsmall, sizeof(Small), hipMemcpyDeviceToHost, s));
+  SELL_HIP(hipStreamSynchronize(s));
+  if (hs.flags) {
+    std::string why;
+    if (hs.flags & 1u) why += " rpt[0] != 0;";
+    if (hs.flags & 2u) why += " rpt decreases;";
+    if (hs.flags & 8u) why += " rpt[nrows] != nnz;";
+    if (hs.flags & 16u) why += " a row is longer than 2^31-1;";
+    if (hs.flags & 4u) why += " column index outside [0, ncols);";
+    return fail(SELL_ERR_BAD_CRS, "sell_build: malformed CRS:" + why);
+  }
+  h->padded = hs.padded;
+  h->max_len = hs.maxlen;
+  h->beta = h->padded == 0 ? 1.0 : (double)h->nnz / (double)h->padded;
+  if (n > 0 && h->nnz > 0) {
+    long double mean = (long double)h->nnz / (long double)n;
+    long double var = (long double)hs.sumsq / (long double)n - mean * mean;
+    if (var < 0) var = 0;
+    h->zeta = (double)(std::sqrt((double)var) / (double)mean);
+  }
+
+  // padded column-major arrays
+  if (h->padded > 0) {
+    h->col = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * (size_t)h->padded));
+    h->val = owned_alloc(h.get(), mem, dtype_size(h->vdt) * (size_t)h->padded);
+    if (!h->col || !h->val) return fail(SELL_ERR_OOM, "sell_build: padded arrays");
+    SELL_HIP(sell::build_fill(A->rpt, A->col, A->val, n, C, h->perm, len, h->cs, nc, h->padded, h->col, h->val,
+                              (int)h->vdt, s));
+  }
+
+  // host copy of the chunk widths, then the work plan
+  h->h_cl.resize((size_t)nc);
+  if (nc > 0) SELL_HIP(hipMemcpyAsync(h->h_cl.data(), h->cl, sizeof(int32_t) * (size_t)nc, hipMemcpyDeviceToHost, s));
+  SELL_HIP(hipStreamSynchronize(s));
+
+  const Geom &g = h->g;
+  h->nitems = nc * g.wpc;
+  ItemSteps st = item_steps(h->h_cl, g);
+  DeviceInfo di = device_info();
+  int32_t S = o.seg_steps > 0 ? o.seg_steps : auto_seg_steps(st.total, di.cus);
+  h->seg_steps = S;
+  if (o.seg_steps >= 0 && st.max > S) {
+    std::vector<sell::Unit> units;
+    std::vector<sell::SplitDesc> splits;
+    int64_t off = 0;
+    // split items first: they are the longest work, so they start earliest
+    for (int64_t it = 0; it < h->nitems; ++it) {
+      int32_t stp = st.steps[(size_t)it];
+      if (stp <= S) continue;
+      int32_t nseg = (stp + S - 1) / S;
+      int32_t sid = (int32_t)splits.size();
+      splits.push_back({(int32_t)it, nseg, off});
+      off += (int64_t)nseg * g.rpw;
+      for (int32_t q = 0; q < nseg; ++q) units.push_back({(int32_t)it, q, nseg, sid});
+    }
+    for (int64_t it = 0; it < h->nitems; ++it)
+      if (st.steps[(size_t)it] <= S) units.push_back({(int32_t)it, 0, 1, 0});
+    h->nunits = (int64_t)units.size();
+    h->nsplit = (int64_t)splits.size();
+    h->nsegs = off / g.rpw;
+    const int64_t kcap = next_pow2(h->kmax);
+    h->units = static_cast<sell::Unit *>(owned_alloc(h.get(), mem, sizeof(sell::Unit) * units.size()));
+    h->splits = static_cast<sell::SplitDesc *>(owned_alloc(h.get(), mem, sizeof(sell::SplitDesc) * splits.size()));
+    h->partial = owned_alloc(h.get(), mem, sizeof(double) * (size_t)(off * kcap));
+    if (!h->units || !h->splits || !h->partial) return fail(SELL_ERR_OOM, "sell_build: work plan");
+    SELL_HIP(hipMemcpyAsync(h->units, units.data(), sizeof(sell::Unit) * units.size(), hipMemcpyHostToDevice, s));
+    SELL_HIP(hipMemcpyAsync(h->splits, splits.data(), sizeof(sell::SplitDesc) * splits.size(),
+                            hipMemcpyHostToDevice, s));
+    SELL_HIP(hipStreamSynchronize(s));
+  } else {
+    h->nunits = h->nitems;
+  }
+  guard.armed = false;
+  *out = h.release();
+  return SELL_OK;
+}
+
+// ===========================================================================
+// Products
+// ===========================================================================
+namespace {
+
+sell::SpmvArgs args_of(const sell_matrix *h, const void *x, void *y) {
+  sell::SpmvArgs a{};
+  a.val = h->val;
+  a.col = h->col;
+  a.cs = h->cs;
+  a.cl = h->cl;
+  a.perm = h->perm;
+  a.x = x;
+  a.y = y;
+  a.nrows = h->nrows;
+  a.nwork = h->units ? h->nunits : h->nitems;
+  a.units = h->units;
+  a.splits = h->splits;
+  a.nsplit = h->units ? h->nsplit : 0;
+  a.partial = h->partial;
+  a.seg_steps = h->seg_steps;
+  a.swizzle = h->units ? 0 : 1;
+  a.k = 1;
+  a.kt = 1;
+  return a;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream) {
+  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_spmv: null handle");
+  if ((h->nrows > 0 && !y) || (h->ncols > 0 && !x)) return fail(SELL_ERR_INVALID_ARG, "sell_spmv: null vector");
+  if (h->nrows == 0) return SELL_OK;
+  sell::SpmvArgs a = args_of(h, x, y);
+  hipError_t e = sell::launch_spmv(h->combo, h->C, h->unroll, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail("sell_spmv launch", e);
+  return SELL_OK;
+}
+
+namespace {
+
+// Right-hand sides per lane (KV) for the block kernel: a power of two <= 8
+// that divides k (aligned vector gathers), with the pass width G*KV not
+// above the next power of two of k.
+int choose_kv(const sell_matrix *h, int k, int ktile) {
+  const int G = h->g.T;
+  int want;
+  if (ktile > 0) want = std::max(1, ktile / G);
+  else want = (int)std::max<int64_t>(1, std::min<int64_t>(next_pow2(k), 16) / G);
+  int kv = 1;
+  while (kv * 2 <= want && kv * 2 <= 8 && k % (kv * 2) == 0) kv *= 2;
+  return kv;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t k, void *stream) {
+  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: null handle");
+  if (k < 1) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k must be >= 1");
+  if ((h->nrows > 0 && !Y) || (h->ncols > 0 && !X)) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: null block");
+  if (h->combo != sell::COMBO_F64_F64) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: FP64 handles only");
+  if (h->nrows == 0) return SELL_OK;
+  if (k == 1) return sell_spmv(h, X, Y, stream);
+  if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: C must be >= 8 for k > 1");
+  if (h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k exceeds the kmax given at build");
+  const int kv = choose_kv(h, k, h->ktile);
+  const int KT = h->g.T * kv;
+  const int64_t ntiles = (k + KT - 1) / KT;
+  if (h->units && ntiles * KT > next_pow2(h->kmax))
+    return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: pass width exceeds the partial-sum buffer");
+  sell::SpmvArgs a = args_of(h, X, Y);
+  a.k = k;
+  a.kt = KT;
+  hipError_t e = sell::launch_spmmv(h->C, kv, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail("sell_spmmv launch", e);
+  return SELL_OK;
+}
+
+// ===========================================================================
+// Inspection
+// ===========================================================================
+extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
+  if (!h || !info) return fail(SELL_ERR_INVALID_ARG, "sell_info: null argument");
+  sell_info_t r{};
+  r.nrows = h->nrows;
+  r.ncols = h->ncols;
+  r.nnz = h->nnz;
+  r.C = h->C;
+  r.sigma = h->sigma;
+  r.nchunks = h->nchunks;
+  r.padded = h->padded;
+  r.beta = h->beta;
+  r.zeta = h->zeta;
+  r.max_row_len = h->max_len;
+  r.val_dtype = h->vdt;
+  r.x_dtype = h->xdt;
+  r.acc_dtype = h->adt;
+  r.lanes_per_row = h->g.T;
+  r.unroll = h->unroll;
+  r.seg_steps = h->seg_steps;
+  r.nunits = h->units ? h->nunits : h->nitems;
+  r.nsplit = h->nsplit;
+  r.has_perm = h->perm ? 1 : 0;
+  r.device_bytes = h->device_bytes;
+  *info = r;
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_export(sell_handle h, int32_t *perm, int32_t *cl, int64_t *cs, int32_t *col, void *val) {
+  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_export: null handle");
+  SELL_HIP(hipDeviceSynchronize());
+  if (perm) {
+    if (h->perm) SELL_HIP(hipMemcpy(perm, h->perm, sizeof(int32_t) * (size_t)h->nrows, hipMemcpyDeviceToHost));
+    else
+      for (int64_t i = 0; i < h->nrows; ++i) perm[i] = (int32_t)i;
+  }
+  if (cl && h->nchunks > 0) SELL_HIP(hipMemcpy(cl, h->cl, sizeof(int32_t) * (size_t)h->nchunks, hipMemcpyDeviceToHost));
+  if (cs) SELL_HIP(hipMemcpy(cs, h->cs, sizeof(int64_t) * (size_t)(h->nchunks + 1), hipMemcpyDeviceToHost));
+  if (col && h->padded > 0) SELL_HIP(hipMemcpy(col, h->col, sizeof(int32_t) * (size_t)h->padded, hipMemcpyDeviceToHost));
+  if (val && h->padded > 0)
+    SELL_HIP(hipMemcpy(val, h->val, dtype_size(h->vdt) * (size_t)h->padded, hipMemcpyDeviceToHost));
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_destroy(sell_handle h) {
+  if (!h) return SELL_OK;
+  (void)hipDeviceSynchronize();
+  free_owned(h);
+  delete h;
+  return SELL_OK;
+}
+
+// ===========================================================================
+// Batched persistent launch
+// ===========================================================================
+struct sell_batch_s {
+  std::vector<sell_handle> hs;
+  int combo = 0, C = 0, U = 8;
+  Geom g{};
+  int32_t seg_steps = 0;
+  int nwaves = 0, grid_blocks = 0;
+  int64_t nunits = 0, nsplit = 0;
+  sell::BatchMat *mats = nullptr;
+  sell::BUnit *units = nullptr;
+  int32_t *slice = nullptr;
+  sell::BSplitDesc *splits = nullptr;
+  void *partial = nullptr;
+  std::vector<sell::BatchMat> host_mats;
+  bool bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void *> owned;
+};
+
+namespace {
+
+void batch_free(sell_batch_s *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void *p : b->owned) (void)hipFree(p);
+  b->owned.clear();
+}
+
+void *batch_alloc(sell_batch_s *b, size_t bytes) {
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  b->owned.push_back(p);
+  return p;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, sell_batch *out) {
+  if (!hs || !out || count < 1) return fail(SELL_ERR_INVALID_ARG, "sell_batch_create: bad arguments");
+  *out = nullptr;
+  for (int32_t b = 0; b < count; ++b)
+    if (!hs[b]) return fail(SELL_ERR_INVALID_ARG, "sell_batch_create: null handle");
+  const sell_handle h0 = hs[0];
+  for (int32_t b = 1; b < count; ++b)
+    if (hs[b]->C != h0->C || hs[b]->combo != h0->combo)
+      return fail(SELL_ERR_UNSUPPORTED, "sell_batch_create: all matrices must share C and dtypes");
+  std::unique_ptr<sell_batch_s> B(new sell_batch_s());
+  struct Guard {
+    sell_batch_s *b;
+    bool armed = true;
+    ~Guard() {
+      if (armed) batch_free(b);
+    }
+  } guard{B.get()};
+  B->hs.assign(hs, hs + count);
+  B->combo = h0->combo;
+  B->C = h0->C;
+  B->U = h0->unroll;
+  B->g = h0->g;
+  const Geom &g = B->g;
+
+  // work of every matrix, one segment length for the whole batch
+  std::vector<ItemSteps> st(count);
+  int64_t total = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    st[b] = item_steps(hs[b]->h_cl, g);
+    total += st[b].total;
+  }
+  DeviceInfo di = device_info();
+  const int32_t S = auto_seg_steps(total, di.cus);
+  B->seg_steps = S;
+  std::vector<sell::BUnit> units;
+  std::vector<int64_t> cost;  // per unit, in wave steps plus a fixed charge
+  std::vector<sell::BSplitDesc> splits;
+  int64_t off = 0;
+  const int64_t kFixed = 4;
+  for (int32_t b = 0; b < count; ++b) {
+    const ItemSteps &s = st[b];
+    for (size_t it = 0; it < s.steps.size(); ++it) {
+      int32_t stp = s.steps[it];
+      if (stp <= S) {
+        units.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
+        cost.push_back(stp + kFixed);
+      } else {
+        int32_t nseg = (stp + S - 1) / S;
+        int32_t sid = (int32_t)splits.size();
+        splits.push_back({b, (int32_t)it, nseg, 0, off});
+        off += (int64_t)nseg * g.rpw;
+        for (int32_t q = 0; q < nseg; ++q) {
+          units.push_back({b, (int32_t)it, q, nseg, sid, {0, 0, 0}});
+          cost.push_back(std::min<int64_t>(S, stp - (int64_t)q * S) + kFixed);
+        }
+      }
+    }
+  }
+  B->nunits = (int64_t)units.size();
+  B->nsplit = (int64_t)splits.size();
+  if (B->nunits >= ((int64_t)1 << 31)) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_create: too many work units");
+
+  // one slice of equal cost per resident wave
+  const int wpcu = std::max(1, sell::batch_waves_per_cu(B->combo, B->C, B->U));
+  int64_t nwaves = (int64_t)di.cus * wpcu;
+  nwaves = std::max<int64_t>(4, std::min<int64_t>(nwaves, B->nunits));
+  nwaves = (nwaves + 3) / 4 * 4;
+  B->nwaves = (int)nwaves;
+  B->grid_blocks = (int)(nwaves / 4);
+  int64_t tot_cost = 0;
+  for (int64_t c : cost) tot_cost += c;
+  std::vector<int32_t> slice((size_t)nwaves + 1, (int32_t)B->nunits);
+  slice[0] = 0;
+  {
+    int64_t acc = 0;
+    int64_t w = 1;
+    for (int64_t u = 0; u < B->nunits && w < nwaves; ++u) {
+      acc += cost[(size_t)u];
+      while (w < nwaves && acc * nwaves >= w * tot_cost) slice[(size_t)w++] = (int32_t)(u + 1);
+    }
+  }
+
+  B->mats = static_cast<sell::BatchMat *>(batch_alloc(B.get(), sizeof(sell::BatchMat) * (size_t)count));
+  B->units = static_cast<sell::BUnit *>(batch_alloc(B.get(), sizeof(sell::BUnit) * units.size()));
+  B->slice = static_cast<int32_t *>(batch_alloc(B.get(), sizeof(int32_t) * slice.size()));
+  B->splits = static_cast<sell::BSplitDesc *>(
+      batch_alloc(B.get(), sizeof(sell::BSplitDesc) * std::max<size_t>(1, splits.size())));
+  B->partial = batch_alloc(B.get(), sizeof(double) * (size_t)std::max<int64_t>(1, off));
+  if (!B->mats || !B->units || !B->slice || !B->splits || !B->partial)
+    return fail(SELL_ERR_OOM, "sell_batch_create: allocation failed");
+  SELL_HIP(hipMemcpy(B->units, units.data(), sizeof(sell::BUnit) * units.size(), hipMemcpyHostToDevice));
+  SELL_HIP(hipMemcpy(B->slice, slice.data(), sizeof(int32_t) * slice.size(), hipMemcpyHostToDevice));
+  if (!splits.empty())
+    SELL_HIP(hipMemcpy(B->splits, splits.data(), sizeof(sell::BSplitDesc) * splits.size(), hipMemcpyHostToDevice));
+  B->host_mats.resize((size_t)count);
+  for (int32_t b = 0; b < count; ++b) {
+    sell::BatchMat &m = B->host_mats[(size_t)b];
+    m.val = hs[b]->val;
+    m.col = hs[b]->col;
+    m.cs = hs[b]->cs;
+    m.cl = hs[b]->cl;
+    m.perm = hs[b]->perm;
+    m.x = nullptr;
+    m.y = nullptr;
+    m.nrows = hs[b]->nrows;
+  }
+
+  // capture the single persistent launch once
+  sell::BatchArgs a{};
+  a.mats = B->mats;
+  a.units = B->units;
+  a.slice = B->slice;
+  a.nwaves = B->nwaves;
+  a.splits = B->splits;
+  a.nsplit = B->nsplit;
+  a.partial = B->partial;
+  a.seg_steps = B->seg_steps;
+  hipStream_t cap = nullptr;
+  SELL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = sell::launch_batch(B->combo, B->C, B->U, a, B->grid_blocks, cap);
+    e = hipStreamEndCapture(cap, &B->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) return hip_fail("sell_batch_create: graph capture", e);
+  guard.armed = false;
+  *out = B.release();
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_batch_spmv(sell_batch b, const void *const *xs, void *const *ys, void *stream) {
+  if (!b || !xs || !ys) return fail(SELL_ERR_INVALID_ARG, "sell_batch_spmv: null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool changed = !b->bound;
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    if ((b->hs[i]->nrows > 0 && !ys[i]) || (b->hs[i]->ncols > 0 && !xs[i]))
+      return fail(SELL_ERR_INVALID_ARG, "sell_batch_spmv: null vector");
+    if (b->host_mats[i].x != xs[i] || b->host_mats[i].y != ys[i]) changed = true;
+  }
+  if (changed) {
+    SELL_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+      b->host_mats[i].x = xs[i];
+      b->host_mats[i].y = ys[i];
+    }
+    SELL_HIP(hipMemcpy(b->mats, b->host_mats.data(), sizeof(sell::BatchMat) * b->host_mats.size(),
+                       hipMemcpyHostToDevice));
+    b->bound = true;
+  }
+  SELL_HIP(hipGraphLaunch(b->exec, s));
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_batch_destroy(sell_batch b) {
+  if (!b) return SELL_OK;
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+  delete b;
+  return SELL_OK;
+}
+
+// ===========================================================================
+// Autotuner
+// ===========================================================================
+extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tune_space *space, void *stream,
+                                     sell_tuned *best) {
+  if (!A || !best || k < 1) return fail(SELL_ERR_INVALID_ARG, "sell_autotune: bad arguments");
+  const int32_t defC[] = {16, 32, 64, 128};
+  const int64_t defS[] = {1};
+  const int32_t defU[] = {4, 8};
+  const int32_t defK[] = {0};
+  sell_tune_space sp{};
+  if (space) sp = *space;
+  const int32_t *Cs = sp.nC > 0 ? sp.C : defC;
+  int nC = sp.nC > 0 ? sp.nC : 4;
+  const int64_t *Ss = sp.nsigma > 0 ? sp.sigma : defS;
+  int nS = sp.nsigma > 0 ? sp.nsigma : 1;
+  const int32_t *Us = sp.nunroll > 0 ? sp.unroll : defU;
+  int nU = sp.nunroll > 0 ? sp.nunroll : 2;
+  const int32_t *Ks = sp.nktile > 0 ? sp.ktile : defK;
+  int nK = sp.nktile > 0 ? sp.nktile : 1;
+  const int reps = sp.reps > 0 ? sp.reps : 20;
+  sell_build_opts o{};
+  o.val_dtype = sp.val_dtype;
+  o.acc_dtype = sp.acc_dtype;
+  if (combo_of(o.val_dtype, o.acc_dtype) < 0) return fail(SELL_ERR_UNSUPPORTED, "sell_autotune: dtype pair");
+  o.kmax = std::max(32, k);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  const size_t xs = (o.val_dtype == SELL_F64 ? 8 : 4), ys = (o.acc_dtype == SELL_F64 ? 8 : 4);
+  Temp tmp(Mem{});
+  void *x = tmp.get(xs * (size_t)std::max<int64_t>(1, A->ncols) * (size_t)k);
+  void *y = tmp.get(ys * (size_t)std::max<int64_t>(1, A->nrows) * (size_t)k);
+  if (!x || !y) return fail(SELL_ERR_OOM, "sell_autotune: vectors");
+  SELL_HIP(hipMemsetAsync(x, 0, xs * (size_t)std::max<int64_t>(1, A->ncols) * (size_t)k, s));
+  hipEvent_t e0, e1;
+  SELL_HIP(hipEventCreate(&e0));
+  SELL_HIP(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } ev{e0, e1};
+
+  sell_tuned r{};
+  r.gflops = -1.0;
+  int cands = 0;
+  for (int ic = 0; ic < nC; ++ic) {
+    for (int is = 0; is < nS; ++is) {
+      sell_handle h = nullptr;
+      sell_status st = sell_build(A, Cs[ic], Ss[is], &o, stream, &h);
+      if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
+      if (st != SELL_OK) return st;
+      for (int iu = 0; iu < nU; ++iu) {
+        if (Us[iu] != 4 && Us[iu] != 8) continue;
+        for (int ik = 0; ik < (k > 1 ? nK : 1); ++ik) {
+          h->unroll = Us[iu];
+          h->ktile = k > 1 ? Ks[ik] : 0;
+          auto call = [&]() { return k > 1 ? sell_spmmv(h, x, y, k, stream) : sell_spmv(h, x, y, stream); };
+          sell_status cs = SELL_OK;
+          for (int w = 0; w < 3 && cs == SELL_OK; ++w) cs = call();
+          if (cs != SELL_OK) continue;
+          (void)hipEventRecord(e0, s);
+          for (int q = 0; q < reps; ++q) call();
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            sell_destroy(h);
+            return hip_fail("sell_autotune: timing", hipGetLastError());
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          double t = (double)ms * 1e-3 / reps;
+          double gf = t > 0 ? 2.0 * (double)A->nnz * k / t * 1e-9 : 0.0;
+          ++cands;
+          if (gf > r.gflops) {
+            r.C = Cs[ic];
+            r.sigma = Ss[is];
+            r.unroll = Us[iu];
+            r.ktile = h->ktile;
+            r.gflops = gf;
+            r.us_per_call = t * 1e6;
+            r.beta = h->beta;
+          }
+        }
+      }
+      sell_destroy(h);
+    }
+  }
+  r.candidates = cands;
+  if (cands == 0) return fail(SELL_ERR_UNSUPPORTED, "sell_autotune: no configuration could be measured");
+  *best = r;
+  return SELL_OK;
+}
+
+// ===========================================================================
+// Bandwidth probes
+// ===========================================================================
+extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps, void *stream, double *gbs) {
+  if (!gbs || reps < 1 || (kind != 0 && kind != 1) || bytes < (1u << 20))
+    return fail(SELL_ERR_INVALID_ARG, "sell_probe_bandwidth: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bytes = bytes / 64 * 64;
+  Temp tmp(Mem{});
+  void *a = tmp.get(kind == 0 ? bytes : bytes / 2);
+  void *b = kind == 1 ? tmp.get(bytes / 2) : nullptr;
+  double *sink = static_cast<double *>(tmp.get(sizeof(double) * 256 * 16));
+  if (!a || !sink || (kind == 1 && !b)) return fail(SELL_ERR_OOM, "sell_probe_bandwidth: buffers");
+  SELL_HIP(hipMemsetAsync(a, 0, kind == 0 ? bytes : bytes / 2, s));
+  auto run = [&]() { return kind == 0 ? sell::probe_read(a, bytes, sink, s) : sell::probe_copy(a, b, bytes / 2, s); };
+  SELL_HIP(run());
+  hipEvent_t e0, e1;
+  SELL_HIP(hipEventCreate(&e0));
+  SELL_HIP(hipEventCreate(&e1));
+  double total_ms = 0.0;
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    (void)hipEventRecord(e0, s);
+    err = run();
+    (void)hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    total_ms += ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail("sell_probe_bandwidth", err);
+  *gbs = (double)bytes * reps / (total_ms * 1e-3) * 1e-9;
+  return SELL_OK;
+}
+
+extern "C" const char *sell_status_string(sell_status s) {
+  switch (s) {
+    case SELL_OK: return "SELL_OK";
+    case SELL_ERR_INVALID_ARG: return "SELL_ERR_INVALID_ARG";
+    case SELL_ERR_BAD_CRS: return "SELL_ERR_BAD_CRS";
+    case SELL_ERR_OOM: return "SELL_ERR_OOM";
+    case SELL_ERR_UNSUPPORTED: return "SELL_ERR_UNSUPPORTED";
+    case SELL_ERR_HIP: return "SELL_ERR_HIP";
+  }
+  return "SELL_ERR_UNKNOWN";
+}
+
+extern "C" const char *sell_last_error(void) { return g_err.c_str(); }

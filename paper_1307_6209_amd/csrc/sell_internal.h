@@ -1,0 +1,193 @@
+// Internal declarations shared by the host orchestration and the kernels of
+// the SELL-C-sigma library (gfx950). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sellcs.h"
+
+namespace sell {
+
+// One work unit of an spMVM launch: a row slice ("item") of a chunk and the
+// range of chunk columns it covers. Items are (chunk, half) pairs: a chunk of
+// C <= 64 rows is one item; C = 128 is two items of 64 rows. A unit with
+// nseg == 1 covers the whole item and writes y directly; otherwise it is
+// segment seg of nseg of split slice sid, and it stores its row sums for the
+// combining kernel.
+struct Unit {
+  int32_t item;
+  int32_t seg;
+  int32_t nseg;
+  int32_t sid;
+};
+
+// A row slice whose chunk is split: its nseg segments stored their row sums
+// at partial[poff + seg*rpw + r] (block form: see k_spmmv); a second kernel
+// adds them in segment order.
+struct SplitDesc {
+  int32_t item;
+  int32_t nseg;
+  int64_t poff;
+};
+
+// Work unit of the batched persistent kernel (adds the matrix index).
+struct BUnit {
+  int32_t mat;
+  int32_t item;
+  int32_t seg;
+  int32_t nseg;
+  int32_t sid;
+  int32_t pad[3];
+};
+
+// Geometry of a chunk height on a 64-lane wavefront.
+struct Geom {
+  int C;    // chunk height
+  int rpw;  // rows of one item (min(C, 64))
+  int T;    // lanes per row inside the wave (64 / rpw)
+  int wpc;  // items (waves) per chunk (C / 64 for C = 128, else 1)
+};
+
+inline Geom geom_of(int C) {
+  Geom g;
+  g.C = C;
+  g.rpw = C < 64 ? C : 64;
+  g.T = 64 / g.rpw;
+  g.wpc = C > 64 ? C / 64 : 1;
+  return g;
+}
+
+// Arguments of the spMVM kernels (by value).
+struct SpmvArgs {
+  const void *val;
+  const int32_t *col;
+  const int64_t *cs;
+  const int32_t *cl;
+  const int32_t *perm;  // nullptr: identity
+  const void *x;
+  void *y;
+  int64_t nrows;
+  int64_t nwork;        // items (no unit list) or units
+  const Unit *units;    // nullptr: wave w handles item w whole
+  const SplitDesc *splits;
+  int64_t nsplit;
+  void *partial;
+  int32_t seg_steps;    // wave steps per segment
+  int32_t swizzle;      // map consecutive work to one XCD
+  // block form only
+  int32_t k;            // right-hand sides
+  int32_t kt;           // right-hand sides per pass (ktile)
+};
+
+// Per-matrix descriptor of the batched kernel (device resident).
+struct BatchMat {
+  const void *val;
+  const int32_t *col;
+  const int64_t *cs;
+  const int32_t *cl;
+  const int32_t *perm;
+  const void *x;
+  void *y;
+  int64_t nrows;
+};
+
+// Split row slice of the batched kernel.
+struct BSplitDesc {
+  int32_t mat;
+  int32_t item;
+  int32_t nseg;
+  int32_t pad;
+  int64_t poff;
+};
+
+struct BatchArgs {
+  const BatchMat *mats;
+  const BUnit *units;
+  const int32_t *slice;  // nwaves + 1 unit offsets
+  int32_t nwaves;
+  const BSplitDesc *splits;
+  int64_t nsplit;
+  void *partial;
+  int32_t seg_steps;
+};
+
+enum DtypeCombo {
+  COMBO_F64_F64 = 0,   // val f64, x f64, acc f64
+  COMBO_F32_F32 = 1,   // val f32, x f32, acc f32
+  COMBO_F32_F64 = 2,   // val f32, x f32, acc f64
+  COMBO_BF16_F32 = 3,  // val bf16, x f32, acc f32
+  COMBO_BF16_F64 = 4,  // val bf16, x f32, acc f64
+};
+
+// Kernel launchers (return hipError of the launch).
+// Each launcher enqueues the product kernel and, when rows are split, the
+// kernel that adds their segment sums.
+hipError_t launch_spmv(int combo, int C, int U, const SpmvArgs &a, hipStream_t s);
+hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
+hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, int grid_blocks, hipStream_t s);
+int batch_waves_per_cu(int combo, int C, int U);
+
+// Build kernels.
+hipError_t build_rowlen(const int64_t *rpt, int64_t n, int64_t nnz, int32_t *len, uint32_t *flags,
+                        unsigned long long *sumsq, int32_t *maxlen, hipStream_t s);
+hipError_t build_colcheck(const int32_t *col, int64_t nnz, int64_t ncols, uint32_t *flags, hipStream_t s);
+// Sorted row order for sigma > 1. keys_a/keys_b: two scratch arrays of n uint64.
+hipError_t build_sort(const int32_t *len, int64_t n, int64_t sigma, uint64_t *keys_a, uint64_t *keys_b,
+                      int32_t *perm, hipStream_t s);
+hipError_t build_chunkwidth(const int32_t *len, const int32_t *perm, int64_t n, int C, int64_t nchunks,
+                            int32_t *cl, int64_t *csz, hipStream_t s);
+// Exclusive scan of n int64 values (in-place allowed); tmp needs scan_tmp_elems(n) int64.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t build_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+hipError_t build_fill(const int64_t *rpt, const int32_t *col, const double *val, int64_t n, int C,
+                      const int32_t *perm, const int32_t *len, const int64_t *cs, int64_t nchunks,
+                      int64_t padded, int32_t *scol, void *sval, int val_dtype, hipStream_t s);
+
+// Bandwidth probes.
+hipError_t probe_read(const void *a, size_t bytes, double *sink, hipStream_t s);
+hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s);
+
+}  // namespace sell
+
+// The handle.
+struct sell_matrix {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  int32_t C = 0;
+  int64_t sigma = 1;
+  sell::Geom g{};
+  int64_t nchunks = 0, padded = 0;
+  int64_t max_len = 0;
+  double beta = 1.0, zeta = 0.0;
+  sell_dtype vdt = SELL_F64, xdt = SELL_F64, adt = SELL_F64;
+  int combo = 0;
+  int32_t unroll = 8;
+  int32_t seg_steps = 0;
+  int32_t ktile = 0;
+  int32_t kmax = 32;
+  int device = 0;
+
+  int32_t *perm = nullptr;
+  int32_t *cl = nullptr;
+  int64_t *cs = nullptr;
+  int32_t *col = nullptr;
+  void *val = nullptr;
+
+  int64_t nitems = 0;
+  int64_t nunits = 0;
+  sell::Unit *units = nullptr;  // nullptr when no chunk is split
+  int64_t nsplit = 0;
+  int64_t nsegs = 0;                  // total segments of split items
+  sell::SplitDesc *splits = nullptr;  // per split id
+  void *partial = nullptr;            // nsegs * rpw * next_pow2(kmax) doubles
+
+  std::vector<int32_t> h_cl;    // host copy of the chunk widths (batch planning)
+
+  sell_allocator alloc{};
+  bool custom_alloc = false;
+  std::vector<std::pair<void *, size_t>> owned;
+  int64_t device_bytes = 0;
+};

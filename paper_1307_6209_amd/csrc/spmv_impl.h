@@ -1,0 +1,460 @@
+// SELL-C-sigma spMVM kernels for gfx950 (64-lane wavefronts).
+//
+// The product y = A x follows Listing "SELL-4-sigma spMVM kernel" of
+// Kreutzer et al. (arXiv:1307.6209), generalised to any C: chunk i holds
+// cl[i] columns of C values stored column by column from cs[i]; lane r of a
+// chunk accumulates val[cs[i] + j*C + r] * x[col[...]] over j, and the sum is
+// stored at y[perm[i*C + r]].
+//
+// Mapping onto a wavefront. A wave owns rpw = min(C, 64) rows of one chunk
+// (C = 128 uses two waves per chunk). When C < 64 the T = 64 / C lanes of a
+// row split its columns: lane l = t*C + r takes columns j = t, t+T, ... so
+// one wave step loads the 64 consecutive slots cs + s*64 + l -- fully
+// coalesced streaming of val and col with no gaps, whatever C is. The T
+// partial sums of a row are then added across lanes (the multiple-threads-
+// per-row scheme the paper discusses for GPUs, Sects. 3.4 and 5.2, done
+// inside one wavefront). val and col are read once, with non-temporal
+// loads, so that the x vector keeps the caches; x is gathered through
+// L2/MALL.
+//
+// Long chunks. A chunk whose width exceeds seg_steps wave steps is cut into
+// segments that run on different waves; each segment stores its row sums in
+// a partial buffer and a second, small kernel adds them in segment order and
+// writes y. The result does not depend on the order the waves ran in, and no
+// cross-wave synchronisation (with its cache write-back and invalidation) is
+// needed inside the product kernel.
+#pragma once
+
+#include "sell_internal.h"
+
+namespace sell {
+namespace dev {
+
+template <int COMBO>
+struct Types;
+template <>
+struct Types<COMBO_F64_F64> {
+  using V = double;
+  using X = double;
+  using A = double;
+};
+template <>
+struct Types<COMBO_F32_F32> {
+  using V = float;
+  using X = float;
+  using A = float;
+};
+template <>
+struct Types<COMBO_F32_F64> {
+  using V = float;
+  using X = float;
+  using A = double;
+};
+template <>
+struct Types<COMBO_BF16_F32> {
+  using V = uint16_t;
+  using X = float;
+  using A = float;
+};
+template <>
+struct Types<COMBO_BF16_F64> {
+  using V = uint16_t;
+  using X = float;
+  using A = double;
+};
+
+// Streaming loads of the matrix arrays (read once per product).
+__device__ __forceinline__ double ld_val(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_val(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_val(const uint16_t *p) {
+  uint32_t b = __builtin_nontemporal_load(p);
+  return __uint_as_float(b << 16);  // bfloat16 -> binary32 is exact
+}
+__device__ __forceinline__ int32_t ld_col(const int32_t *p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ double fmac(double v, double x, double acc) { return __builtin_fma(v, x, acc); }
+__device__ __forceinline__ double fmac(float v, float x, double acc) {
+  return __builtin_fma((double)v, (double)x, acc);  // the product is exact in double
+}
+__device__ __forceinline__ float fmac(float v, float x, float acc) { return __builtin_fmaf(v, x, acc); }
+
+// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).
+// Renumber them so that each XCD receives one contiguous range of the work:
+// rows that are close share x entries, and then share one L2.
+__device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, rem = nb & 7;
+  const int64_t x = b & 7, i = b >> 3;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
+constexpr int kWavesPerBlock = 4;
+
+// One work unit: rows [h*rpw, (h+1)*rpw) of chunk `chunk`, wave steps
+// [seg*seg_steps, ...) of it (all of them when nseg == 1).
+template <int COMBO, int C, int U>
+__device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const int32_t *__restrict__ col,
+                                          const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
+                                          const int32_t *__restrict__ perm, const void *__restrict__ xv,
+                                          void *__restrict__ yv, int64_t nrows, int32_t item, int32_t seg,
+                                          int32_t nseg, int64_t poff, void *__restrict__ partial,
+                                          int32_t seg_steps, int lane) {
+  using V = typename Types<COMBO>::V;
+  using X = typename Types<COMBO>::X;
+  using A = typename Types<COMBO>::A;
+  constexpr int RPW = C < 64 ? C : 64;
+  constexpr int T = 64 / RPW;
+  constexpr int WPC = C > 64 ? C / 64 : 1;
+  constexpr int64_t STRIDE = (int64_t)T * C;  // slots between two steps of a lane
+
+  const int64_t chunk = item / WPC;
+  const int h = item - (int)(chunk * WPC);
+  const int rl = lane % RPW, t = lane / RPW;
+  const int r = h * RPW + rl;
+  const int64_t base = cs[chunk];
+  const int cl = clp[chunk];
+  const int steps = (cl + T - 1) / T;
+  int sb = 0, se = steps;
+  if (nseg > 1) {
+    sb = seg * seg_steps;
+    se = sb + seg_steps < steps ? sb + seg_steps : steps;
+  }
+  // steps in which every lane's column exists
+  const int full = se < cl / T ? se : cl / T;
+  const int32_t *cp = col + base + (int64_t)t * C + r;
+  const V *vp = static_cast<const V *>(valv) + base + (int64_t)t * C + r;
+  const X *x = static_cast<const X *>(xv);
+
+  A acc = 0;
+  int s = sb;
+  for (; s + U <= full; s += U) {
+    int32_t ci[U];
+    decltype(ld_val(vp)) vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ci[u] = ld_col(cp + (int64_t)(s + u) * STRIDE);
+      vv[u] = ld_val(vp + (int64_t)(s + u) * STRIDE);
+    }
+    X xg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xg[u] = x[ci[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = fmac(vv[u], xg[u], acc);
+  }
+  if (s < se) {  // at most U steps remain; the last one may be partial
+    int32_t ci[U];
+    decltype(ld_val(vp)) vv[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ss = s + u;
+      ok[u] = ss < se && ss * T + t < cl;
+      ci[u] = ok[u] ? ld_col(cp + (int64_t)ss * STRIDE) : 0;
+      vv[u] = ok[u] ? ld_val(vp + (int64_t)ss * STRIDE) : 0;
+    }
+    X xg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xg[u] = ok[u] ? x[ci[u]] : (X)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) acc = fmac(vv[u], xg[u], acc);
+  }
+  // add the T partial sums of each row (lanes r, r + C, r + 2C, ...)
+#pragma unroll
+  for (int off = 32; off >= RPW; off >>= 1) acc += __shfl_xor(acc, off);
+
+  A *y = static_cast<A *>(yv);
+  const int64_t p = chunk * C + r;
+  if (nseg == 1) {
+    if (t == 0 && p < nrows) {
+      const int64_t row = perm ? (int64_t)perm[p] : p;
+      __builtin_nontemporal_store(acc, y + row);
+    }
+    return;
+  }
+  // segment of a split row slice: leave the sums for the combining kernel
+  if (t == 0) static_cast<A *>(partial)[poff + seg * RPW + rl] = acc;
+}
+
+// Adds the segment sums of split row slices in segment order and writes y.
+// One wave per split slice.
+template <int COMBO, int C>
+__device__ __forceinline__ void combine_split(const SplitDesc d, const int32_t *__restrict__ perm,
+                                              const void *__restrict__ partial, void *__restrict__ yv,
+                                              int64_t nrows, int lane) {
+  using A = typename Types<COMBO>::A;
+  constexpr int RPW = C < 64 ? C : 64;
+  constexpr int WPC = C > 64 ? C / 64 : 1;
+  if (lane >= RPW) return;
+  const int64_t chunk = d.item / WPC;
+  const int h = d.item - (int)(chunk * WPC);
+  const int64_t p = chunk * C + h * RPW + lane;
+  if (p >= nrows) return;
+  const A *part = static_cast<const A *>(partial) + d.poff + lane;
+  A sum = 0;
+  for (int q = 0; q < d.nseg; ++q) sum += part[(int64_t)q * RPW];
+  const int64_t row = perm ? (int64_t)perm[p] : p;
+  static_cast<A *>(yv)[row] = sum;
+}
+
+template <int COMBO, int C>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_combine(SpmvArgs a) {
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w >= a.nsplit) return;
+  combine_split<COMBO, C>(a.splits[w], a.perm, a.partial, a.y, a.nrows, threadIdx.x & 63);
+}
+
+template <int COMBO, int C, int U>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = a.swizzle ? xcd_swizzle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t w = b * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w >= a.nwork) return;
+  int32_t item, seg = 0, nseg = 1;
+  int64_t poff = 0;
+  if (a.units) {
+    const Unit u = a.units[w];
+    item = u.item;
+    seg = u.seg;
+    nseg = u.nseg;
+    if (nseg > 1) poff = a.splits[u.sid].poff;
+  } else {
+    item = (int32_t)w;
+  }
+  spmv_unit<COMBO, C, U>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff, a.partial,
+                         a.seg_steps, lane);
+}
+
+// Persistent batched form: wave w runs units [slice[w], slice[w+1]) of the
+// concatenated work of all matrices.
+template <int COMBO, int C, int U>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w >= a.nwaves) return;
+  const int32_t u0 = a.slice[w], u1 = a.slice[w + 1];
+  for (int32_t q = u0; q < u1; ++q) {
+    const BUnit u = a.units[q];
+    const BatchMat m = a.mats[u.mat];
+    const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
+    spmv_unit<COMBO, C, U>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg, poff,
+                           a.partial, a.seg_steps, lane);
+  }
+}
+
+template <int COMBO, int C>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch_combine(BatchArgs a) {
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w >= a.nsplit) return;
+  const BSplitDesc b = a.splits[w];
+  const BatchMat m = a.mats[b.mat];
+  combine_split<COMBO, C>(SplitDesc{b.item, b.nseg, b.poff}, m.perm, a.partial, m.y, m.nrows, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------------------
+// Block form Y = A X (FP64), X row-major ncols x k. A wave owns rpw rows of a
+// chunk and KT = G*KV right-hand sides (G = 64 / rpw lanes per row, KV
+// contiguous right-hand sides per lane; lane = r*G + g). Every matrix entry
+// is loaded once per pass and multiplies KT contiguous values of X.
+// blockIdx.y selects the pass (right-hand sides [y*KT, (y+1)*KT)).
+// ---------------------------------------------------------------------------
+template <int KV>
+struct DVec {
+  typedef double type __attribute__((ext_vector_type(KV)));
+};
+template <>
+struct DVec<1> {
+  typedef double type;
+};
+
+template <int KV>
+__device__ __forceinline__ double vget(const typename DVec<KV>::type &v, int i) {
+  return v[i];
+}
+template <>
+__device__ __forceinline__ double vget<1>(const double &v, int) {
+  return v;
+}
+
+template <int C, int KV>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
+  constexpr int RPW = C < 64 ? C : 64;
+  constexpr int G = 64 / RPW;
+  constexpr int WPC = C > 64 ? C / 64 : 1;
+  constexpr int KT = G * KV;
+  constexpr int U = 2;
+  using VecT = typename DVec<KV>::type;
+
+  const int lane = threadIdx.x & 63;
+  const int64_t b = a.swizzle ? xcd_swizzle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t w = b * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w >= a.nwork) return;
+  int32_t item, seg = 0, nseg = 1;
+  int64_t poff = 0;
+  if (a.units) {
+    const Unit u = a.units[w];
+    item = u.item;
+    seg = u.seg;
+    nseg = u.nseg;
+    if (nseg > 1) poff = a.splits[u.sid].poff;
+  } else {
+    item = (int32_t)w;
+  }
+  const int k = a.k;
+  const int tile = blockIdx.y;
+  const int rl = lane / G, g = lane % G;
+  const int v0 = tile * KT + g * KV;  // first right-hand side of this lane
+  const bool active = v0 < k;          // k % KV == 0: a lane's KV values are all in range or all out
+
+  const int64_t chunk = item / WPC;
+  const int h = item - (int)(chunk * WPC);
+  const int r = h * RPW + rl;
+  const int64_t base = a.cs[chunk];
+  const int cl = a.cl[chunk];
+  int jb = 0, je = cl;
+  if (nseg > 1) {
+    jb = seg * a.seg_steps * G;
+    je = jb + a.seg_steps * G < cl ? jb + a.seg_steps * G : cl;
+  }
+  const int32_t *cp = a.col + base + r;
+  const double *vp = static_cast<const double *>(a.val) + base + r;
+  const double *X = static_cast<const double *>(a.x);
+
+  double acc[KV];
+#pragma unroll
+  for (int v = 0; v < KV; ++v) acc[v] = 0.0;
+  int j = jb;
+  for (; j + U <= je; j += U) {
+    int32_t ci[U];
+    double vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ci[u] = ld_col(cp + (int64_t)(j + u) * C);
+      vv[u] = ld_val(vp + (int64_t)(j + u) * C);
+    }
+    if (active) {
+      VecT xg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xg[u] = *reinterpret_cast<const VecT *>(X + (int64_t)ci[u] * k + v0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < KV; ++v) acc[v] = __builtin_fma(vv[u], vget<KV>(xg[u], v), acc[v]);
+    }
+  }
+  for (; j < je; ++j) {
+    const int32_t c = ld_col(cp + (int64_t)j * C);
+    const double vj = ld_val(vp + (int64_t)j * C);
+    if (active) {
+      const VecT xg = *reinterpret_cast<const VecT *>(X + (int64_t)c * k + v0);
+#pragma unroll
+      for (int v = 0; v < KV; ++v) acc[v] = __builtin_fma(vj, vget<KV>(xg, v), acc[v]);
+    }
+  }
+
+  double *Y = static_cast<double *>(a.y);
+  const int64_t p = chunk * C + r;
+  if (nseg == 1) {
+    if (active && p < a.nrows) {
+      const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
+#pragma unroll
+      for (int v = 0; v < KV; ++v) __builtin_nontemporal_store(acc[v], Y + row * k + v0 + v);
+    }
+    return;
+  }
+  // segment of a split row slice: the sums of pass `tile` go to
+  // partial[(poff*ntiles + tile*nseg*RPW + seg*RPW + rl)*KT + g*KV + v]
+  if (active) {
+    double *mine = static_cast<double *>(a.partial) +
+                   ((poff * gridDim.y + (int64_t)tile * nseg * RPW + (int64_t)seg * RPW + rl) * KT + g * KV);
+#pragma unroll
+    for (int v = 0; v < KV; ++v) mine[v] = acc[v];
+  }
+}
+
+// Block form: add the segment sums of split row slices. Block (w, tile):
+// split slice w, pass tile; lanes cover RPW rows x KT right-hand sides.
+template <int C>
+__global__ void __launch_bounds__(64) k_combine_mm(SpmvArgs a) {
+  constexpr int RPW = C < 64 ? C : 64;
+  constexpr int WPC = C > 64 ? C / 64 : 1;
+  const SplitDesc d = a.splits[blockIdx.x];
+  const int tile = blockIdx.y, ntiles = gridDim.y, KT = a.kt, k = a.k;
+  const int64_t chunk = d.item / WPC;
+  const int h = d.item - (int)(chunk * WPC);
+  const double *base = static_cast<const double *>(a.partial) + (d.poff * ntiles + (int64_t)tile * d.nseg * RPW) * KT;
+  double *Y = static_cast<double *>(a.y);
+  for (int e = threadIdx.x; e < RPW * KT; e += 64) {
+    const int rl = e / KT, vl = e - rl * KT;
+    const int v = tile * KT + vl;
+    const int64_t p = chunk * C + h * RPW + rl;
+    if (v >= k || p >= a.nrows) continue;
+    double sum = 0.0;
+    for (int q = 0; q < d.nseg; ++q) sum += base[((int64_t)q * RPW + rl) * KT + vl];
+    const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
+    Y[row * k + v] = sum;
+  }
+}
+
+}  // namespace dev
+}  // namespace sell
+
+namespace sell {
+namespace dev {
+
+// Host-side launchers for one dtype combination; every supported (C, U)
+// pair is instantiated.
+#define SELL_FOR_EACH_CU(X) \
+  X(1, 4) X(1, 8) X(2, 4) X(2, 8) X(4, 4) X(4, 8) X(8, 4) X(8, 8) X(16, 4) X(16, 8) X(32, 4) X(32, 8) X(64, 4) \
+      X(64, 8) X(128, 4) X(128, 8)
+
+template <int COMBO>
+hipError_t launch_spmv_t(int C, int U, const SpmvArgs &a, hipStream_t s) {
+  if (a.nwork <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((a.nwork + kWavesPerBlock - 1) / kWavesPerBlock);
+#define SELL_L(CC, UU)                                                                                      \
+  if (C == CC && U == UU) {                                                                                \
+    hipLaunchKernelGGL((k_spmv<COMBO, CC, UU>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);            \
+    hipError_t e_ = hipGetLastError();                                                                     \
+    if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                      \
+    const unsigned nbc = (unsigned)((a.nsplit + kWavesPerBlock - 1) / kWavesPerBlock);                      \
+    hipLaunchKernelGGL((k_combine<COMBO, CC>), dim3(nbc), dim3(64 * kWavesPerBlock), 0, s, a);             \
+    return hipGetLastError();                                                                              \
+  }
+  SELL_FOR_EACH_CU(SELL_L)
+#undef SELL_L
+  return hipErrorInvalidValue;
+}
+
+template <int COMBO>
+hipError_t launch_batch_t(int C, int U, const BatchArgs &a, int grid_blocks, hipStream_t s) {
+#define SELL_L(CC, UU)                                                                                     \
+  if (C == CC && U == UU) {                                                                               \
+    hipLaunchKernelGGL((k_batch<COMBO, CC, UU>), dim3(grid_blocks), dim3(64 * kWavesPerBlock), 0, s, a);  \
+    hipError_t e_ = hipGetLastError();                                                                    \
+    if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                     \
+    const unsigned nbc = (unsigned)((a.nsplit + kWavesPerBlock - 1) / kWavesPerBlock);                     \
+    hipLaunchKernelGGL((k_batch_combine<COMBO, CC>), dim3(nbc), dim3(64 * kWavesPerBlock), 0, s, a);      \
+    return hipGetLastError();                                                                             \
+  }
+  SELL_FOR_EACH_CU(SELL_L)
+#undef SELL_L
+  return hipErrorInvalidValue;
+}
+
+template <int COMBO>
+int batch_waves_per_cu_t(int C, int U) {
+  int blocks = 0;
+#define SELL_L(CC, UU)                                                                                              \
+  if (C == CC && U == UU) {                                                                                        \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<COMBO, CC, UU>, 64 * kWavesPerBlock, 0) != \
+        hipSuccess)                                                                                                \
+      blocks = 1;                                                                                                  \
+    return blocks * kWavesPerBlock;                                                                                \
+  }
+  SELL_FOR_EACH_CU(SELL_L)
+#undef SELL_L
+  return kWavesPerBlock;
+}
+
+}  // namespace dev
+}  // namespace sell

@@ -1,0 +1,297 @@
+"""Python binding of the SELL-C-sigma C ABI (include/sellcs.h).
+
+Argument marshalling only: every step of the build and of the products runs
+in the HIP kernels of libsellcs.so. torch supplies device memory (tensors)
+and streams (``torch.cuda.current_stream()`` unless one is given). There is
+no CPU path: if the shared library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsellcs.so")
+_lib = None
+
+SELL_OK, SELL_ERR_INVALID_ARG, SELL_ERR_BAD_CRS, SELL_ERR_OOM, SELL_ERR_UNSUPPORTED, SELL_ERR_HIP = range(6)
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
+DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
+
+
+class SellError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__("%s: %s (%s)" % (where, detail, _status_name(status)))
+
+
+c_i32, c_i64, c_p, c_d = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+
+
+class SellCrs(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("nnz", c_i64), ("rpt", c_p), ("col", c_p), ("val", c_p)]
+
+
+class SellAllocator(ctypes.Structure):
+    _fields_ = [("alloc", c_p), ("free", c_p), ("ctx", c_p)]
+
+
+class SellBuildOpts(ctypes.Structure):
+    _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("seg_steps", c_i32),
+                ("ktile", c_i32), ("kmax", c_i32), ("alloc", ctypes.POINTER(SellAllocator))]
+
+
+class SellInfo(ctypes.Structure):
+    _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("nnz", c_i64), ("C", c_i32), ("sigma", c_i64),
+                ("nchunks", c_i64), ("padded", c_i64), ("beta", c_d), ("zeta", c_d), ("max_row_len", c_i64),
+                ("val_dtype", ctypes.c_int), ("x_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int),
+                ("lanes_per_row", c_i32), ("unroll", c_i32), ("seg_steps", c_i32), ("nunits", c_i64),
+                ("nsplit", c_i64), ("has_perm", c_i32), ("device_bytes", c_i64)]
+
+
+class SellTuneSpace(ctypes.Structure):
+    _fields_ = [("C", ctypes.POINTER(c_i32)), ("nC", c_i32), ("sigma", ctypes.POINTER(c_i64)), ("nsigma", c_i32),
+                ("unroll", ctypes.POINTER(c_i32)), ("nunroll", c_i32), ("ktile", ctypes.POINTER(c_i32)),
+                ("nktile", c_i32), ("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("reps", c_i32)]
+
+
+class SellTuned(ctypes.Structure):
+    _fields_ = [("C", c_i32), ("sigma", c_i64), ("unroll", c_i32), ("ktile", c_i32), ("gflops", c_d),
+                ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32)]
+
+
+# Every entry point the header declares: name -> (restype, argtypes).
+SIGNATURES = {
+    "sell_build": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, c_i64, ctypes.POINTER(SellBuildOpts), c_p,
+                                  ctypes.POINTER(c_p)]),
+    "sell_spmv": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
+    "sell_spmmv": (ctypes.c_int, [c_p, c_p, c_p, c_i32, c_p]),
+    "sell_info": (ctypes.c_int, [c_p, ctypes.POINTER(SellInfo)]),
+    "sell_export": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p, c_p]),
+    "sell_destroy": (ctypes.c_int, [c_p]),
+    "sell_batch_create": (ctypes.c_int, [ctypes.POINTER(c_p), c_i32, ctypes.POINTER(c_p)]),
+    "sell_batch_spmv": (ctypes.c_int, [c_p, ctypes.POINTER(c_p), ctypes.POINTER(c_p), c_p]),
+    "sell_batch_destroy": (ctypes.c_int, [c_p]),
+    "sell_autotune": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, ctypes.POINTER(SellTuneSpace), c_p,
+                                     ctypes.POINTER(SellTuned)]),
+    "sell_probe_bandwidth": (ctypes.c_int, [c_i32, ctypes.c_size_t, c_i32, c_p, ctypes.POINTER(c_d)]),
+    "sell_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sell_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded libsellcs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsellcs.so is not built (run: python -m paper_1307_6209_amd._build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().sell_status_string(s).decode()
+    except Exception:
+        return str(s)
+
+
+def _check(status: int, where: str):
+    if status != SELL_OK:
+        raise SellError(status, where, lib().sell_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dptr(t, dtype, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _torch_dtype(code: int):
+    import torch
+    return {0: torch.float64, 1: torch.float32}[code]
+
+
+class SellMatrix:
+    """A device-resident SELL-C-sigma matrix (wraps a sell_handle)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        self.info = sell_info(self)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("matrix already destroyed")
+        return self._h
+
+    @property
+    def x_dtype(self):
+        return _torch_dtype(self.info["x_dtype"])
+
+    @property
+    def y_dtype(self):
+        return _torch_dtype(self.info["acc_dtype"])
+
+    def close(self):
+        if self._h:
+            _check(lib().sell_destroy(self._h), "sell_destroy")
+            self._h = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and not sys.is_finalizing():
+            try:
+                lib().sell_destroy(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
+               unroll: int = 0, seg_steps: int = 0, ktile: int = 0, kmax: int = 0, stream=None) -> SellMatrix:
+    """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64)."""
+    import torch
+    nrows = rpt.numel() - 1
+    nnz = col.numel()
+    A = SellCrs(nrows, int(ncols), nnz, _dptr(rpt, torch.int64, "rpt"), _dptr(col, torch.int32, "col"),
+                _dptr(val, torch.float64, "val", nnz))
+    if acc_dtype is None:
+        acc_dtype = "f64" if val_dtype == "f64" else "f32"
+    o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, seg_steps, ktile, kmax, None)
+    h = c_p()
+    _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
+    return SellMatrix(h)
+
+
+def sell_spmv(h: SellMatrix, x, y, stream=None):
+    """y = A x on the stream (asynchronous)."""
+    xp = _dptr(x, h.x_dtype, "x", h.info["ncols"])
+    yp = _dptr(y, h.y_dtype, "y", h.info["nrows"])
+    _check(lib().sell_spmv(h.handle, xp, yp, _stream(stream)), "sell_spmv")
+    return y
+
+
+def sell_spmmv(h: SellMatrix, X, Y, stream=None):
+    """Y = A X for row-major X (ncols x k) and Y (nrows x k)."""
+    if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y must be 2-D with the same number of columns")
+    k = X.shape[1]
+    if X.shape[0] != h.info["ncols"] or Y.shape[0] != h.info["nrows"]:
+        raise ValueError("X must be ncols x k and Y nrows x k")
+    xp = _dptr(X, h.x_dtype, "X")
+    yp = _dptr(Y, h.y_dtype, "Y")
+    _check(lib().sell_spmmv(h.handle, xp, yp, k, _stream(stream)), "sell_spmmv")
+    return Y
+
+
+def sell_info(h: SellMatrix) -> dict:
+    info = SellInfo()
+    _check(lib().sell_info(h.handle, ctypes.byref(info)), "sell_info")
+    return {name: getattr(info, name) for name, _ in SellInfo._fields_}
+
+
+def sell_export(h: SellMatrix) -> dict:
+    """Host copies (numpy) of perm, cl, cs, col and val (bf16 as uint16 bits)."""
+    inf = h.info
+    perm = np.empty(inf["nrows"], np.int32)
+    cl = np.empty(inf["nchunks"], np.int32)
+    cs = np.empty(inf["nchunks"] + 1, np.int64)
+    col = np.empty(inf["padded"], np.int32)
+    vdt = {0: np.float64, 1: np.float32, 2: np.uint16}[inf["val_dtype"]]
+    val = np.empty(inf["padded"], vdt)
+    p = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    _check(lib().sell_export(h.handle, p(perm), p(cl), p(cs), p(col), p(val)), "sell_export")
+    return dict(perm=perm, cl=cl, cs=cs, col=col, val=val)
+
+
+def sell_destroy(h: SellMatrix):
+    h.close()
+
+
+class SellBatch:
+    def __init__(self, handle, mats):
+        self._h = handle
+        self.mats = list(mats)  # keep the matrices alive
+
+    def close(self):
+        if self._h:
+            _check(lib().sell_batch_destroy(self._h), "sell_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and not sys.is_finalizing():
+            try:
+                lib().sell_batch_destroy(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def sell_batch_create(mats) -> SellBatch:
+    arr = (c_p * len(mats))(*[m.handle for m in mats])
+    b = c_p()
+    _check(lib().sell_batch_create(arr, len(mats), ctypes.byref(b)), "sell_batch_create")
+    return SellBatch(b, mats)
+
+
+def sell_batch_spmv(b: SellBatch, xs, ys, stream=None):
+    n = len(b.mats)
+    if len(xs) != n or len(ys) != n:
+        raise ValueError("need one x and one y per matrix")
+    xa = (c_p * n)(*[_dptr(x, m.x_dtype, "xs[%d]" % i, m.info["ncols"]).value for i, (x, m) in enumerate(zip(xs, b.mats))])
+    ya = (c_p * n)(*[_dptr(y, m.y_dtype, "ys[%d]" % i, m.info["nrows"]).value for i, (y, m) in enumerate(zip(ys, b.mats))])
+    _check(lib().sell_batch_spmv(b._h, xa, ya, _stream(stream)), "sell_batch_spmv")
+    return ys
+
+
+def sell_batch_destroy(b: SellBatch):
+    b.close()
+
+
+def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=(), ktile=(),
+                  val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0, stream=None) -> dict:
+    """Time every configuration of the search space; return the fastest."""
+    import torch
+    nrows = rpt.numel() - 1
+    nnz = col.numel()
+    A = SellCrs(nrows, int(ncols), nnz, _dptr(rpt, torch.int64, "rpt"), _dptr(col, torch.int32, "col"),
+                _dptr(val, torch.float64, "val", nnz))
+    if acc_dtype is None:
+        acc_dtype = "f64" if val_dtype == "f64" else "f32"
+    arrs = [(c_i32 * len(C))(*C), (c_i64 * len(sigma))(*sigma), (c_i32 * len(unroll))(*unroll),
+            (c_i32 * len(ktile))(*ktile)]
+    sp = SellTuneSpace(arrs[0], len(C), arrs[1], len(sigma), arrs[2], len(unroll), arrs[3], len(ktile),
+                       DTYPES[val_dtype], DTYPES[acc_dtype], reps)
+    r = SellTuned()
+    _check(lib().sell_autotune(ctypes.byref(A), k, ctypes.byref(sp), _stream(stream), ctypes.byref(r)), "sell_autotune")
+    return {name: getattr(r, name) for name, _ in SellTuned._fields_}
+
+
+def sell_probe_bandwidth(kind: int, nbytes: int, reps: int = 10, stream=None) -> float:
+    """Read-only (kind 0) or copy (kind 1) bandwidth in GB/s."""
+    g = c_d()
+    _check(lib().sell_probe_bandwidth(kind, nbytes, reps, _stream(stream), ctypes.byref(g)), "sell_probe_bandwidth")
+    return g.value

@@ -1,0 +1,81 @@
+"""The C ABI library loads and exports every entry point include/sellcs.h
+declares; argument checks that happen on the host return the documented
+status codes. No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sellcs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    names = re.findall(r"^\s*(?:sell_status|const\s+char\s*\*)\s*(sell_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1307_6209_amd import sellcs
+    if not os.path.exists(sellcs.LIB_PATH):
+        from paper_1307_6209_amd import _build
+        _build.build()
+    return sellcs.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["sell_build", "sell_spmv", "sell_spmmv", "sell_export", "sell_info", "sell_destroy",
+                 "sell_batch_create", "sell_batch_spmv", "sell_batch_destroy", "sell_autotune",
+                 "sell_probe_bandwidth", "sell_status_string", "sell_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_the_header():
+    from paper_1307_6209_amd import sellcs
+    assert sorted(sellcs.SIGNATURES) == declared_functions()
+
+
+def test_status_strings(L):
+    for code, name in enumerate(["SELL_OK", "SELL_ERR_INVALID_ARG", "SELL_ERR_BAD_CRS", "SELL_ERR_OOM",
+                                 "SELL_ERR_UNSUPPORTED", "SELL_ERR_HIP"]):
+        assert L.sell_status_string(code).decode() == name
+
+
+def test_host_side_argument_errors(L):
+    from paper_1307_6209_amd import sellcs
+    h = ctypes.c_void_p()
+    assert L.sell_build(None, 32, 1, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    assert b"null" in L.sell_last_error()
+    # pointers are not dereferenced before the arguments are checked
+    A = sellcs.SellCrs(10, 10, 0, ctypes.c_void_p(8), None, None)
+    for C in [0, 3, 256, -4]:
+        assert L.sell_build(ctypes.byref(A), C, 1, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    assert L.sell_build(ctypes.byref(A), 32, 0, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    Aneg = sellcs.SellCrs(-1, 10, 0, ctypes.c_void_p(8), None, None)
+    assert L.sell_build(ctypes.byref(Aneg), 32, 1, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    Abig = sellcs.SellCrs(2**31, 10, 0, ctypes.c_void_p(8), None, None)
+    assert L.sell_build(ctypes.byref(Abig), 32, 1, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    f64_val_f32_acc = sellcs.SellBuildOpts(0, 1, 0, 0, 0, 0, None)  # FP64 values need FP64 accumulation
+    assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(f64_val_f32_acc), None,
+                        ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    badu = sellcs.SellBuildOpts(0, 0, 5, 0, 0, 0, None)
+    assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badu), None, ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    assert L.sell_spmv(None, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_spmmv(None, None, None, 4, None) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_batch_create(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    g = ctypes.c_double()
+    assert L.sell_probe_bandwidth(7, 1 << 30, 1, None, ctypes.byref(g)) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_autotune(None, 1, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_destroy(None) == sellcs.SELL_OK
+    assert L.sell_batch_destroy(None) == sellcs.SELL_OK

@@ -1,0 +1,88 @@
+"""One persistent hipGraph-captured launch over many matrices of uneven
+size: each result against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import build, check_fp64, check_reduced, say
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(count, seed, lo=1000, hi=20000):
+    sizes = synth.batch_sizes(count, seed, lo, hi)
+    return [synth.powerlaw(int(n), seed=seed * 100 + b) for b, n in enumerate(sizes)]
+
+
+def run(b, mats, xs, dtype):
+    import torch
+    from paper_1307_6209_amd import sellcs
+    xd = [torch.from_numpy(np.ascontiguousarray(x)).cuda().to(dtype[0]) for x in xs]
+    yd = [torch.full((A.nrows,), float("nan"), dtype=dtype[1], device="cuda") for A in mats]
+    sellcs.sell_batch_spmv(b, xd, yd)
+    torch.cuda.synchronize()
+    return [y.double().cpu().numpy() for y in yd]
+
+
+@pytest.mark.parametrize("C", [16, 32, 64, 128])
+def test_batch_fp64(C):
+    import torch
+    from paper_1307_6209_amd import sellcs
+    mats = make_batch(12, 3)
+    sigmas = [1, C, 256, 4096, 10**9, 1, 512, 1, 2048, C, 1, 100000]
+    hs = [build(A, C, s) for A, s in zip(mats, sigmas)]
+    b = sellcs.sell_batch_create(hs)
+    xs = [synth.uniform(A.ncols, 50 + i, 1) for i, A in enumerate(mats)]
+    say("batch C", C, "rows", sum(A.nrows for A in mats))
+    ys = run(b, mats, xs, (torch.float64, torch.float64))
+    for A, x, y in zip(mats, xs, ys):
+        check_fp64(A, y, x)
+    # a second call with new vectors (the pointer table is rewritten)
+    xs2 = [synth.uniform(A.ncols, 80 + i, 1) for i, A in enumerate(mats)]
+    ys2 = run(b, mats, xs2, (torch.float64, torch.float64))
+    for A, x, y in zip(mats, xs2, ys2):
+        check_fp64(A, y, x)
+    b.close()
+
+
+def test_batch_repeat_same_pointers_is_deterministic():
+    import torch
+    from paper_1307_6209_amd import sellcs
+    mats = make_batch(20, 4, 1000, 50000)
+    hs = [build(A, 32, 64) for A in mats]
+    b = sellcs.sell_batch_create(hs)
+    xd = [torch.from_numpy(synth.uniform(A.ncols, 9, 1)).cuda() for A in mats]
+    yd = [torch.empty(A.nrows, dtype=torch.float64, device="cuda") for A in mats]
+    sellcs.sell_batch_spmv(b, xd, yd)
+    torch.cuda.synchronize()
+    first = [y.cpu().numpy().copy() for y in yd]
+    for _ in range(5):
+        sellcs.sell_batch_spmv(b, xd, yd)
+    torch.cuda.synchronize()
+    for f, y in zip(first, yd):
+        assert np.array_equal(f, y.cpu().numpy())
+    for A, x, y in zip(mats, xd, first):
+        check_fp64(A, y, x.cpu().numpy())
+
+
+@pytest.mark.parametrize("val_dtype,acc", [("f32", "f32"), ("bf16", "f64")])
+def test_batch_reduced(val_dtype, acc):
+    import torch
+    from paper_1307_6209_amd import sellcs
+    mats = make_batch(6, 5)
+    hs = [build(A, 32, 128, val_dtype=val_dtype, acc_dtype=acc) for A in mats]
+    b = sellcs.sell_batch_create(hs)
+    xs = [oracle.round_f32(synth.uniform(A.ncols, 60 + i, 1)).astype(np.float64) for i, A in enumerate(mats)]
+    ys = run(b, mats, xs, (torch.float32, torch.float64 if acc == "f64" else torch.float32))
+    for A, h, x, y in zip(mats, hs, xs, ys):
+        # compare with the single-matrix launch, which check_reduced pins to the oracle
+        check_reduced(A, h, x, val_dtype, acc, 32, nseg_max=64)
+
+
+def test_batch_mixed_C_rejected():
+    from paper_1307_6209_amd import sellcs
+    mats = make_batch(2, 6)
+    hs = [build(mats[0], 32, 1), build(mats[1], 64, 1)]
+    with pytest.raises(sellcs.SellError):
+        sellcs.sell_batch_create(hs)

@@ -1,0 +1,35 @@
+"""Bandwidth probes and the autotuner."""
+import pytest
+
+import synth
+from gpu_util import dev_crs, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_probes_plausible():
+    from paper_1307_6209_amd import sellcs
+    r = sellcs.sell_probe_bandwidth(0, 2 << 30, 5)
+    c = sellcs.sell_probe_bandwidth(1, 2 << 30, 5)
+    say("read GB/s", r, "copy GB/s", c)
+    assert 1000 < r < 8000 * 1.02
+    assert 1000 < c < 8000 * 1.02
+
+
+def test_autotune_small():
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(100_000, seed=71)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(16, 32, 64), sigma=(1, 64, 4096), unroll=(4, 8), reps=5)
+    say("autotune", r)
+    assert r["C"] in (16, 32, 64) and r["sigma"] in (1, 64, 4096) and r["unroll"] in (4, 8)
+    assert r["candidates"] == 18 and r["gflops"] > 0
+
+
+def test_autotune_block():
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(50_000, seed=72)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=8, C=(16, 32), sigma=(1, 256), unroll=(8,), ktile=(0, 4, 8),
+                             reps=3)
+    assert r["candidates"] == 12 and r["ktile"] in (0, 4, 8)

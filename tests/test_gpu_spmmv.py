@@ -1,0 +1,79 @@
+"""Block form Y = A X (k right-hand sides, row-major) against the oracle:
+every column within 1e-13 (|A||X|)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import build, say
+
+pytestmark = pytest.mark.gpu
+
+
+def run_spmmv(h, X):
+    import torch
+    from paper_1307_6209_amd import sellcs
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    Y = torch.full((h.info["nrows"], X.shape[1]), float("nan"), dtype=torch.float64, device="cuda")
+    sellcs.sell_spmmv(h, Xd, Y)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy()
+
+
+def check(A, Y, X, tol=1e-13):
+    Yh, aY = oracle.crs_spmmv_hi(A, X)
+    assert np.all(np.isfinite(Y))
+    assert np.all(np.abs(Y - Yh) <= tol * aY)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16, 32])
+@pytest.mark.parametrize("C,sigma", [(8, 1), (16, 1), (32, 64), (64, 1), (128, 1000)])
+def test_spmmv(k, C, sigma):
+    A = synth.powerlaw(30_000, seed=41)
+    X = synth.block_vector(A.ncols, k, seed=42)
+    say("spmmv k", k, "C", C, "sigma", sigma)
+    h = build(A, C, sigma, seg_steps=-1)
+    check(A, run_spmmv(h, X), X)
+
+
+@pytest.mark.parametrize("ktile", [1, 2, 4, 8, 16, 32, 64])
+def test_spmmv_ktile(ktile):
+    A = synth.random_crs(700, 900, seed=43, max_len=60, empty_frac=0.1, duplicates=True, unsorted=True)
+    X = synth.block_vector(A.ncols, 16, seed=44)
+    h = build(A, 16, 1, ktile=ktile)
+    check(A, run_spmmv(h, X), X)
+
+
+@pytest.mark.parametrize("k", [2, 8, 32])
+@pytest.mark.parametrize("C", [16, 32, 128])
+def test_spmmv_split(k, C):
+    A = synth.powerlaw(30_000, seed=45)
+    X = synth.block_vector(A.ncols, k, seed=46)
+    h = build(A, C, 1, seg_steps=3)
+    assert h.info["nsplit"] > 0
+    Y1 = run_spmmv(h, X)
+    check(A, Y1, X)
+    assert np.array_equal(run_spmmv(h, X), Y1)
+
+
+def test_spmmv_k_above_kmax_rejected():
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(30_000, seed=47)
+    h = build(A, 32, 1, seg_steps=3, kmax=8)
+    with pytest.raises(sellcs.SellError):
+        run_spmmv(h, synth.block_vector(A.ncols, 16))
+    check(A, run_spmmv(h, synth.block_vector(A.ncols, 8)), synth.block_vector(A.ncols, 8))
+
+
+def test_spmmv_columns_equal_spmv():
+    """Column v of Y equals the single-vector product of column v of X
+    within the FP64 bound (summation orders differ)."""
+    from gpu_util import spmv_gpu, check_fp64
+    A = synth.stencil27(16)
+    X = synth.block_vector(A.ncols, 4, seed=48)
+    h = build(A, 32, 1)
+    Y = run_spmmv(h, X)
+    for v in range(4):
+        y = spmv_gpu(h, X[:, v].copy())
+        check_fp64(A, y, X[:, v].copy())
+        check_fp64(A, Y[:, v].copy(), X[:, v].copy())
