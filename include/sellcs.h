@@ -70,9 +70,12 @@ typedef struct {
 typedef struct {
   sell_dtype val_dtype; /* storage of the matrix values: F64, F32 or BF16 */
   sell_dtype acc_dtype; /* accumulation and y: F64 or F32 (F64 values need F64) */
-  int32_t unroll;       /* chunk columns in flight per lane: 0 auto, else 4 or 8 */
-  int32_t seg_steps;    /* longest run of wave steps one work unit covers before a
-                           chunk is split across waves: 0 auto, < 0 never split */
+  int32_t unroll;       /* matrix slots in flight per lane: 0 auto, else 4 or 8 */
+  int32_t vec;          /* consecutive slots (rows) each lane loads at once: 0 auto,
+                           else 1, 2 or 4 (2 and 4 need C <= 64 and vec <= C) */
+  int32_t seg_cols;     /* widest chunk one work unit covers, in chunk columns,
+                           before the chunk is split across waves (rounded up to
+                           a multiple of 64): 0 auto, < 0 never split */
   int32_t ktile;        /* right-hand sides per pass in sell_spmmv: 0 auto, else a
                            power of two <= 64 */
   int32_t kmax;         /* largest k sell_spmmv will be called with on matrices
@@ -93,7 +96,8 @@ typedef struct {
   sell_dtype val_dtype, x_dtype, acc_dtype;
   int32_t lanes_per_row; /* lanes of one wavefront that share a row (64 / C, or 1) */
   int32_t unroll;
-  int32_t seg_steps;     /* split threshold in wave steps */
+  int32_t vec;
+  int32_t seg_cols;      /* split threshold in chunk columns */
   int64_t nunits;        /* work units of one sell_spmv launch */
   int64_t nsplit;        /* row slices whose chunk is split over several waves */
   int32_t has_perm;      /* 0 when the row order is the identity (sigma == 1) */

@@ -120,34 +120,52 @@ void free_owned(sell_matrix *h) {
   h->owned.clear();
 }
 
-// Split plan of one matrix for a given segment length (in wave steps).
-struct ItemSteps {
-  std::vector<int32_t> steps;  // per item
-  int64_t total = 0;
+// Work of one matrix: per item (row slice) its width in chunk columns, and
+// the number of wave steps all items take together.
+struct ItemCols {
+  std::vector<int32_t> cols;  // per item
+  int64_t total_steps = 0;
   int32_t max = 0;
 };
 
-ItemSteps item_steps(const std::vector<int32_t> &cl, const Geom &g) {
-  ItemSteps r;
-  r.steps.resize(cl.size() * (size_t)g.wpc);
+ItemCols item_cols(const std::vector<int32_t> &cl, const Geom &g) {
+  ItemCols r;
+  r.cols.resize(cl.size() * (size_t)g.wpc);
   for (size_t c = 0; c < cl.size(); ++c) {
-    int32_t st = (cl[c] + g.T - 1) / g.T;
-    for (int h = 0; h < g.wpc; ++h) r.steps[c * g.wpc + h] = st;
-    r.total += (int64_t)st * g.wpc;
-    r.max = std::max(r.max, st);
+    for (int h = 0; h < g.wpc; ++h) r.cols[c * g.wpc + h] = cl[c];
+    r.total_steps += (int64_t)((cl[c] + g.T - 1) / g.T) * g.wpc;
+    r.max = std::max(r.max, cl[c]);
   }
   return r;
 }
 
-// Automatic segment length: long enough that a unit amortises its fixed
-// cost, short enough that no unit is much longer than an average wave's
-// share of the whole product (resident waves: CUs x 32).
-int32_t auto_seg_steps(int64_t total_steps, int cus) {
-  int64_t resident = (int64_t)cus * 32;
-  int64_t s = total_steps / (2 * resident);
-  if (s < 64) s = 64;
-  if (s > (1 << 20)) s = 1 << 20;
+// Slots per lane when the caller leaves it open: two for FP64 values (one
+// 16-byte access), one for FP32 and BF16 values (measured fastest on the
+// 27-point stencil).
+int default_vec(int C, sell_dtype v) {
+  int V = v == SELL_F64 ? 2 : 1;
+  if (C > 64) return 1;
+  while (V > C) V >>= 1;
+  return V;
+}
+
+int32_t round_seg(int64_t cols) {
+  int64_t a = sell::kSegAlign;
+  int64_t s = (cols + a - 1) / a * a;
+  if (s < a) s = a;
+  if (s > (1 << 30)) s = 1 << 30;
   return (int32_t)s;
+}
+
+// Automatic segment width: long enough that a unit amortises its fixed
+// cost (at least 64 wave steps), short enough that no unit is much longer
+// than an average wave's share of the whole product (resident waves:
+// CUs x 32). Converted from wave steps to chunk columns.
+int32_t auto_seg_cols(int64_t total_steps, int T, int cus) {
+  int64_t resident = (int64_t)cus * 32;
+  int64_t steps = total_steps / (2 * resident);
+  if (steps < 64) steps = 64;
+  return round_seg(steps * T);
 }
 
 }  // namespace
@@ -176,6 +194,10 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
   if (combo < 0) return fail(SELL_ERR_UNSUPPORTED, "sell_build: unsupported (value, accumulation) dtype pair");
   if (o.unroll != 0 && o.unroll != 4 && o.unroll != 8)
     return fail(SELL_ERR_UNSUPPORTED, "sell_build: unroll must be 0, 4 or 8");
+  if (o.vec != 0 && o.vec != 1 && o.vec != 2 && o.vec != 4)
+    return fail(SELL_ERR_UNSUPPORTED, "sell_build: vec must be 0, 1, 2 or 4");
+  if (o.vec > 1 && (C > 64 || o.vec > C))
+    return fail(SELL_ERR_UNSUPPORTED, "sell_build: vec > 1 needs C <= 64 and vec <= C");
   if (o.ktile < 0 || o.ktile > 64 || (o.ktile & (o.ktile - 1)) != 0)
     return fail(SELL_ERR_UNSUPPORTED, "sell_build: ktile must be 0 or a power of two <= 64");
   if (o.kmax < 0) return fail(SELL_ERR_INVALID_ARG, "sell_build: kmax must be >= 0");
@@ -189,7 +211,7 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
   h->nnz = A->nnz;
   h->C = C;
   h->sigma = sigma;
-  h->g = sell::geom_of(C);
+  h->g = sell::geom_of(C, o.vec ? o.vec : default_vec(C, o.val_dtype));
   h->vdt = o.val_dtype;
   h->adt = o.acc_dtype;
   h->xdt = o.val_dtype == SELL_F64 ? SELL_F64 : SELL_F32;
@@ -292,26 +314,26 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
 
   const Geom &g = h->g;
   h->nitems = nc * g.wpc;
-  ItemSteps st = item_steps(h->h_cl, g);
+  ItemCols st = item_cols(h->h_cl, g);
   DeviceInfo di = device_info();
-  int32_t S = o.seg_steps > 0 ? o.seg_steps : auto_seg_steps(st.total, di.cus);
-  h->seg_steps = S;
-  if (o.seg_steps >= 0 && st.max > S) {
+  int32_t S = o.seg_cols > 0 ? round_seg(o.seg_cols) : auto_seg_cols(st.total_steps, g.T, di.cus);
+  h->seg_cols = S;
+  if (o.seg_cols >= 0 && st.max > S) {
     std::vector<sell::Unit> units;
     std::vector<sell::SplitDesc> splits;
     int64_t off = 0;
     // split items first: they are the longest work, so they start earliest
     for (int64_t it = 0; it < h->nitems; ++it) {
-      int32_t stp = st.steps[(size_t)it];
-      if (stp <= S) continue;
-      int32_t nseg = (stp + S - 1) / S;
+      int32_t w = st.cols[(size_t)it];
+      if (w <= S) continue;
+      int32_t nseg = (w + S - 1) / S;
       int32_t sid = (int32_t)splits.size();
       splits.push_back({(int32_t)it, nseg, off});
       off += (int64_t)nseg * g.rpw;
       for (int32_t q = 0; q < nseg; ++q) units.push_back({(int32_t)it, q, nseg, sid});
     }
     for (int64_t it = 0; it < h->nitems; ++it)
-      if (st.steps[(size_t)it] <= S) units.push_back({(int32_t)it, 0, 1, 0});
+      if (st.cols[(size_t)it] <= S) units.push_back({(int32_t)it, 0, 1, 0});
     h->nunits = (int64_t)units.size();
     h->nsplit = (int64_t)splits.size();
     h->nsegs = off / g.rpw;
@@ -352,7 +374,7 @@ sell::SpmvArgs args_of(const sell_matrix *h, const void *x, void *y) {
   a.splits = h->splits;
   a.nsplit = h->units ? h->nsplit : 0;
   a.partial = h->partial;
-  a.seg_steps = h->seg_steps;
+  a.seg_cols = h->seg_cols;
   a.swizzle = h->units ? 0 : 1;
   a.k = 1;
   a.kt = 1;
@@ -366,7 +388,7 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   if ((h->nrows > 0 && !y) || (h->ncols > 0 && !x)) return fail(SELL_ERR_INVALID_ARG, "sell_spmv: null vector");
   if (h->nrows == 0) return SELL_OK;
   sell::SpmvArgs a = args_of(h, x, y);
-  hipError_t e = sell::launch_spmv(h->combo, h->C, h->unroll, a, static_cast<hipStream_t>(stream));
+  hipError_t e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail("sell_spmv launch", e);
   return SELL_OK;
 }
@@ -377,7 +399,7 @@ namespace {
 // that divides k (aligned vector gathers), with the pass width G*KV not
 // above the next power of two of k.
 int choose_kv(const sell_matrix *h, int k, int ktile) {
-  const int G = h->g.T;
+  const int G = 64 / h->g.rpw;
   int want;
   if (ktile > 0) want = std::max(1, ktile / G);
   else want = (int)std::max<int64_t>(1, std::min<int64_t>(next_pow2(k), 16) / G);
@@ -398,7 +420,7 @@ extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: C must be >= 8 for k > 1");
   if (h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k exceeds the kmax given at build");
   const int kv = choose_kv(h, k, h->ktile);
-  const int KT = h->g.T * kv;
+  const int KT = (64 / h->g.rpw) * kv;
   const int64_t ntiles = (k + KT - 1) / KT;
   if (h->units && ntiles * KT > next_pow2(h->kmax))
     return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: pass width exceeds the partial-sum buffer");
@@ -431,7 +453,8 @@ extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
   r.acc_dtype = h->adt;
   r.lanes_per_row = h->g.T;
   r.unroll = h->unroll;
-  r.seg_steps = h->seg_steps;
+  r.vec = h->g.V;
+  r.seg_cols = h->seg_cols;
   r.nunits = h->units ? h->nunits : h->nitems;
   r.nsplit = h->nsplit;
   r.has_perm = h->perm ? 1 : 0;
@@ -471,7 +494,7 @@ struct sell_batch_s {
   std::vector<sell_handle> hs;
   int combo = 0, C = 0, U = 8;
   Geom g{};
-  int32_t seg_steps = 0;
+  int32_t seg_cols = 0;
   int nwaves = 0, grid_blocks = 0;
   int64_t nunits = 0, nsplit = 0;
   sell::BatchMat *mats = nullptr;
@@ -528,39 +551,39 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   B->combo = h0->combo;
   B->C = h0->C;
   B->U = h0->unroll;
-  B->g = h0->g;
+  B->g = sell::geom_of(h0->C, 1);  // the batched kernel loads one slot per lane
   const Geom &g = B->g;
 
-  // work of every matrix, one segment length for the whole batch
-  std::vector<ItemSteps> st(count);
+  // work of every matrix, one segment width for the whole batch
+  std::vector<ItemCols> st(count);
   int64_t total = 0;
   for (int32_t b = 0; b < count; ++b) {
-    st[b] = item_steps(hs[b]->h_cl, g);
-    total += st[b].total;
+    st[b] = item_cols(hs[b]->h_cl, g);
+    total += st[b].total_steps;
   }
   DeviceInfo di = device_info();
-  const int32_t S = auto_seg_steps(total, di.cus);
-  B->seg_steps = S;
+  const int32_t S = auto_seg_cols(total, g.T, di.cus);
+  B->seg_cols = S;
   std::vector<sell::BUnit> units;
   std::vector<int64_t> cost;  // per unit, in wave steps plus a fixed charge
   std::vector<sell::BSplitDesc> splits;
   int64_t off = 0;
   const int64_t kFixed = 4;
   for (int32_t b = 0; b < count; ++b) {
-    const ItemSteps &s = st[b];
-    for (size_t it = 0; it < s.steps.size(); ++it) {
-      int32_t stp = s.steps[it];
-      if (stp <= S) {
+    const ItemCols &s = st[b];
+    for (size_t it = 0; it < s.cols.size(); ++it) {
+      int32_t w = s.cols[it];
+      if (w <= S) {
         units.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
-        cost.push_back(stp + kFixed);
+        cost.push_back((w + g.T - 1) / g.T + kFixed);
       } else {
-        int32_t nseg = (stp + S - 1) / S;
+        int32_t nseg = (w + S - 1) / S;
         int32_t sid = (int32_t)splits.size();
         splits.push_back({b, (int32_t)it, nseg, 0, off});
         off += (int64_t)nseg * g.rpw;
         for (int32_t q = 0; q < nseg; ++q) {
           units.push_back({b, (int32_t)it, q, nseg, sid, {0, 0, 0}});
-          cost.push_back(std::min<int64_t>(S, stp - (int64_t)q * S) + kFixed);
+          cost.push_back((std::min<int64_t>(S, w - (int64_t)q * S) + g.T - 1) / g.T + kFixed);
         }
       }
     }
@@ -623,7 +646,7 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   a.splits = B->splits;
   a.nsplit = B->nsplit;
   a.partial = B->partial;
-  a.seg_steps = B->seg_steps;
+  a.seg_cols = B->seg_cols;
   hipStream_t cap = nullptr;
   SELL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -728,7 +751,7 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
       for (int iu = 0; iu < nU; ++iu) {
         if (Us[iu] != 4 && Us[iu] != 8) continue;
         for (int ik = 0; ik < (k > 1 ? nK : 1); ++ik) {
-          h->unroll = Us[iu];
+          h->unroll = std::max(Us[iu], h->g.V);
           h->ktile = k > 1 ? Ks[ik] : 0;
           auto call = [&]() { return k > 1 ? sell_spmmv(h, x, y, k, stream) : sell_spmv(h, x, y, stream); };
           sell_status cs = SELL_OK;

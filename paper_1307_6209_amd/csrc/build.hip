@@ -32,34 +32,51 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 constexpr uint32_t F_RPT0 = 1u, F_DECR = 2u, F_COL = 4u, F_RPTN = 8u, F_LONG = 16u;
 
 // len[i] = rpt[i+1] - rpt[i]; flags for a malformed rpt; sum of squared
-// lengths (for the coefficient of variation) and the longest row.
+// lengths (for the coefficient of variation) and the longest row. A fixed
+// grid strides over the rows and reduces per block, so the three global
+// atomics are issued once per block, not once per wave.
 __global__ void __launch_bounds__(kBlock) k_rowlen(const int64_t *__restrict__ rpt, int64_t n, int64_t nnz,
                                                    int32_t *__restrict__ len, uint32_t *flags,
                                                    unsigned long long *sumsq, int32_t *maxlen) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ unsigned long long s_sq[kBlock / 64];
+  __shared__ int32_t s_mx[kBlock / 64];
+  __shared__ uint32_t s_f[kBlock / 64];
   uint32_t f = 0;
-  int32_t l = 0;
-  if (i < n) {
+  int32_t mx = 0;
+  unsigned long long sq = 0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     int64_t d = rpt[i + 1] - rpt[i];
     if (d < 0) f |= F_DECR;
     if (d > 0x7fffffffLL) f |= F_LONG;
-    l = (d < 0 || d > 0x7fffffffLL) ? 0 : (int32_t)d;
+    int32_t l = (d < 0 || d > 0x7fffffffLL) ? 0 : (int32_t)d;
     len[i] = l;
+    sq += (unsigned long long)l * (unsigned long long)l;
+    mx = l > mx ? l : mx;
   }
-  if (i == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (rpt[0] != 0) f |= F_RPT0;
     if (rpt[n] != nnz) f |= F_RPTN;
   }
-  unsigned long long sq = (unsigned long long)l * (unsigned long long)l;
   sq = wave_sum_u64(sq);
-  int32_t mx = wave_max(l);
-  // any lane's flags, merged over the wave
-  uint32_t fw = f;
-  for (int off = 32; off > 0; off >>= 1) fw |= __shfl_xor(fw, off);
+  mx = wave_max(mx);
+  for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off);
+  const int w = threadIdx.x >> 6;
   if (lane_id() == 0) {
+    s_sq[w] = sq;
+    s_mx[w] = mx;
+    s_f[w] = f;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kBlock / 64; ++k) {
+      sq += s_sq[k];
+      mx = s_mx[k] > mx ? s_mx[k] : mx;
+      f |= s_f[k];
+    }
     if (sq) atomicAdd(sumsq, sq);
     if (mx) atomicMax(maxlen, mx);
-    if (fw) atomicOr(flags, fw);
+    if (f) atomicOr(flags, f);
   }
 }
 
@@ -341,6 +358,7 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 hipError_t build_rowlen(const int64_t *rpt, int64_t n, int64_t nnz, int32_t *len, uint32_t *flags,
                         unsigned long long *sumsq, int32_t *maxlen, hipStream_t s) {
   unsigned nb = blocks_for(n > 0 ? n : 1, kBlock);
+  if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_rowlen, dim3(nb), dim3(kBlock), 0, s, rpt, n, nnz, len, flags, sumsq, maxlen);
   return hipGetLastError();
 }

@@ -44,22 +44,29 @@ struct BUnit {
   int32_t pad[3];
 };
 
-// Geometry of a chunk height on a 64-lane wavefront.
+// Geometry of a chunk height on a 64-lane wavefront whose lanes each hold
+// V consecutive slots of a wave step (V > 1 only for C <= 64).
 struct Geom {
   int C;    // chunk height
+  int V;    // slots (rows) per lane
   int rpw;  // rows of one item (min(C, 64))
-  int T;    // lanes per row inside the wave (64 / rpw)
+  int T;    // chunk columns per wave step (64 * V / rpw)
   int wpc;  // items (waves) per chunk (C / 64 for C = 128, else 1)
 };
 
-inline Geom geom_of(int C) {
+inline Geom geom_of(int C, int V = 1) {
   Geom g;
   g.C = C;
+  g.V = V;
   g.rpw = C < 64 ? C : 64;
-  g.T = 64 / g.rpw;
+  g.T = 64 * V / g.rpw;
   g.wpc = C > 64 ? C / 64 : 1;
   return g;
 }
+
+// Segments of split chunks are whole multiples of this many chunk columns,
+// so that every kernel's step width (at most 64 columns) divides them.
+constexpr int kSegAlign = 64;
 
 // Arguments of the spMVM kernels (by value).
 struct SpmvArgs {
@@ -76,7 +83,7 @@ struct SpmvArgs {
   const SplitDesc *splits;
   int64_t nsplit;
   void *partial;
-  int32_t seg_steps;    // wave steps per segment
+  int32_t seg_cols;     // chunk columns per segment (multiple of kSegAlign)
   int32_t swizzle;      // map consecutive work to one XCD
   // block form only
   int32_t k;            // right-hand sides
@@ -112,7 +119,7 @@ struct BatchArgs {
   const BSplitDesc *splits;
   int64_t nsplit;
   void *partial;
-  int32_t seg_steps;
+  int32_t seg_cols;
 };
 
 enum DtypeCombo {
@@ -126,7 +133,7 @@ enum DtypeCombo {
 // Kernel launchers (return hipError of the launch).
 // Each launcher enqueues the product kernel and, when rows are split, the
 // kernel that adds their segment sums.
-hipError_t launch_spmv(int combo, int C, int U, const SpmvArgs &a, hipStream_t s);
+hipError_t launch_spmv(int combo, int C, int U, int V, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, int grid_blocks, hipStream_t s);
 int batch_waves_per_cu(int combo, int C, int U);
@@ -165,7 +172,7 @@ struct sell_matrix {
   sell_dtype vdt = SELL_F64, xdt = SELL_F64, adt = SELL_F64;
   int combo = 0;
   int32_t unroll = 8;
-  int32_t seg_steps = 0;
+  int32_t seg_cols = 0;
   int32_t ktile = 0;
   int32_t kmax = 32;
   int device = 0;

@@ -17,7 +17,7 @@
 // loads, so that the x vector keeps the caches; x is gathered through
 // L2/MALL.
 //
-// Long chunks. A chunk whose width exceeds seg_steps wave steps is cut into
+// Long chunks. A chunk wider than seg_cols columns is cut into
 // segments that run on different waves; each segment stores its row sums in
 // a partial buffer and a second, small kernel adds them in segment order and
 // writes y. The result does not depend on the order the waves ran in, and no
@@ -63,14 +63,27 @@ struct Types<COMBO_BF16_F64> {
   using A = double;
 };
 
-// Streaming loads of the matrix arrays (read once per product).
-__device__ __forceinline__ double ld_val(const double *p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ float ld_val(const float *p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ float ld_val(const uint16_t *p) {
-  uint32_t b = __builtin_nontemporal_load(p);
-  return __uint_as_float(b << 16);  // bfloat16 -> binary32 is exact
+// Streaming (non-temporal) loads of N consecutive elements; N > 1 uses one
+// vector access, so the base must be aligned to N elements.
+template <int N, typename T>
+__device__ __forceinline__ void ld_stream(const T *p, T (&out)[N]) {
+  if constexpr (N == 1) {
+    out[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef T vt __attribute__((ext_vector_type(N)));
+    const vt v = __builtin_nontemporal_load(reinterpret_cast<const vt *>(p));
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v[i];
+  }
 }
+
+__device__ __forceinline__ double ld_val(const double *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ int32_t ld_col(const int32_t *p) { return __builtin_nontemporal_load(p); }
+
+// Stored value -> arithmetic type (bfloat16 -> binary32 is exact).
+__device__ __forceinline__ double cvt(double v) { return v; }
+__device__ __forceinline__ float cvt(float v) { return v; }
+__device__ __forceinline__ float cvt(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ __forceinline__ double fmac(double v, double x, double acc) { return __builtin_fma(v, x, acc); }
 __device__ __forceinline__ double fmac(float v, float x, double acc) {
@@ -89,90 +102,121 @@ __device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t nb) {
 
 constexpr int kWavesPerBlock = 4;
 
-// One work unit: rows [h*rpw, (h+1)*rpw) of chunk `chunk`, wave steps
-// [seg*seg_steps, ...) of it (all of them when nseg == 1).
-template <int COMBO, int C, int U>
+// One work unit: rows [h*rpw, (h+1)*rpw) of chunk `chunk`, chunk columns
+// [seg*seg_cols, ...) of it (all of them when nseg == 1).
+//
+// Lane l holds the VV consecutive slots VV*l .. VV*l+VV-1 of every wave step
+// (64*VV consecutive slots = T chunk columns of RPW rows): rows
+// rl0 .. rl0+VV-1 with rl0 = (VV*l) % RPW, column offset t = (VV*l) / RPW.
+template <int COMBO, int C, int U, int VV>
 __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const int32_t *__restrict__ col,
                                           const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
                                           const int32_t *__restrict__ perm, const void *__restrict__ xv,
                                           void *__restrict__ yv, int64_t nrows, int32_t item, int32_t seg,
                                           int32_t nseg, int64_t poff, void *__restrict__ partial,
-                                          int32_t seg_steps, int lane) {
+                                          int32_t seg_cols, int lane) {
   using V = typename Types<COMBO>::V;
   using X = typename Types<COMBO>::X;
   using A = typename Types<COMBO>::A;
   constexpr int RPW = C < 64 ? C : 64;
-  constexpr int T = 64 / RPW;
+  static_assert(VV == 1 || C <= 64, "several slots per lane need C <= 64");
+  static_assert(RPW % VV == 0, "VV must divide the rows of an item");
+  constexpr int T = 64 * VV / RPW;          // chunk columns per wave step
   constexpr int WPC = C > 64 ? C / 64 : 1;
+  constexpr int LPC = RPW / VV;             // lanes covering one chunk column
   constexpr int64_t STRIDE = (int64_t)T * C;  // slots between two steps of a lane
 
   const int64_t chunk = item / WPC;
   const int h = item - (int)(chunk * WPC);
-  const int rl = lane % RPW, t = lane / RPW;
-  const int r = h * RPW + rl;
+  const int rl0 = (VV * lane) % RPW, t = (VV * lane) / RPW;
   const int64_t base = cs[chunk];
   const int cl = clp[chunk];
-  const int steps = (cl + T - 1) / T;
-  int sb = 0, se = steps;
+  int jb = 0, je = cl;
   if (nseg > 1) {
-    sb = seg * seg_steps;
-    se = sb + seg_steps < steps ? sb + seg_steps : steps;
+    jb = seg * seg_cols;
+    je = jb + seg_cols < cl ? jb + seg_cols : cl;
   }
-  // steps in which every lane's column exists
-  const int full = se < cl / T ? se : cl / T;
-  const int32_t *cp = col + base + (int64_t)t * C + r;
-  const V *vp = static_cast<const V *>(valv) + base + (int64_t)t * C + r;
+  const int sb = jb / T, se = (je + T - 1) / T;
+  const int full = je / T;  // steps below this one hold a real column in every lane
+  const int64_t off0 = base + (int64_t)t * C + h * RPW + rl0;
+  const int32_t *cp = col + off0;
+  const V *vp = static_cast<const V *>(valv) + off0;
   const X *x = static_cast<const X *>(xv);
 
-  A acc = 0;
+  A acc[VV];
+#pragma unroll
+  for (int v = 0; v < VV; ++v) acc[v] = 0;
   int s = sb;
   for (; s + U <= full; s += U) {
-    int32_t ci[U];
-    decltype(ld_val(vp)) vv[U];
+    int32_t ci[U][VV];
+    V raw[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ci[u] = ld_col(cp + (int64_t)(s + u) * STRIDE);
-      vv[u] = ld_val(vp + (int64_t)(s + u) * STRIDE);
+      ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
+      ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
     }
-    X xg[U];
+    X xg[U][VV];
 #pragma unroll
-    for (int u = 0; u < U; ++u) xg[u] = x[ci[u]];
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc = fmac(vv[u], xg[u], acc);
+      for (int v = 0; v < VV; ++v) xg[u][v] = x[ci[u][v]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xg[u][v], acc[v]);
   }
   if (s < se) {  // at most U steps remain; the last one may be partial
-    int32_t ci[U];
-    decltype(ld_val(vp)) vv[U];
+    int32_t ci[U][VV];
+    V raw[U][VV];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int ss = s + u;
-      ok[u] = ss < se && ss * T + t < cl;
-      ci[u] = ok[u] ? ld_col(cp + (int64_t)ss * STRIDE) : 0;
-      vv[u] = ok[u] ? ld_val(vp + (int64_t)ss * STRIDE) : 0;
-    }
-    X xg[U];
+      ok[u] = ss < se && ss * T + t < je;
+      if (ok[u]) {
+        ld_stream<VV>(cp + (int64_t)ss * STRIDE, ci[u]);
+        ld_stream<VV>(vp + (int64_t)ss * STRIDE, raw[u]);
+      } else {
 #pragma unroll
-    for (int u = 0; u < U; ++u) xg[u] = ok[u] ? x[ci[u]] : (X)0;
+        for (int v = 0; v < VV; ++v) {
+          ci[u][v] = 0;
+          raw[u][v] = 0;
+        }
+      }
+    }
+    X xg[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) acc = fmac(vv[u], xg[u], acc);
-  }
-  // add the T partial sums of each row (lanes r, r + C, r + 2C, ...)
 #pragma unroll
-  for (int off = 32; off >= RPW; off >>= 1) acc += __shfl_xor(acc, off);
+      for (int v = 0; v < VV; ++v) xg[u][v] = ok[u] ? x[ci[u][v]] : (X)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) {
+#pragma unroll
+        for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xg[u][v], acc[v]);
+      }
+  }
+  // add the T partial sums of each row: lanes l, l + LPC, l + 2*LPC, ...
+#pragma unroll
+  for (int off = 32; off >= LPC; off >>= 1)
+#pragma unroll
+    for (int v = 0; v < VV; ++v) acc[v] += __shfl_xor(acc[v], off);
 
   A *y = static_cast<A *>(yv);
-  const int64_t p = chunk * C + r;
+  const int64_t p0 = chunk * C + h * RPW + rl0;
+  if (t != 0) return;
   if (nseg == 1) {
-    if (t == 0 && p < nrows) {
-      const int64_t row = perm ? (int64_t)perm[p] : p;
-      __builtin_nontemporal_store(acc, y + row);
+#pragma unroll
+    for (int v = 0; v < VV; ++v) {
+      const int64_t p = p0 + v;
+      if (p < nrows) __builtin_nontemporal_store(acc[v], y + (perm ? (int64_t)perm[p] : p));
     }
     return;
   }
   // segment of a split row slice: leave the sums for the combining kernel
-  if (t == 0) static_cast<A *>(partial)[poff + seg * RPW + rl] = acc;
+  A *part = static_cast<A *>(partial) + poff + (int64_t)seg * RPW + rl0;
+#pragma unroll
+  for (int v = 0; v < VV; ++v) part[v] = acc[v];
 }
 
 // Adds the segment sums of split row slices in segment order and writes y.
@@ -203,7 +247,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_combine(SpmvArgs a) {
   combine_split<COMBO, C>(a.splits[w], a.perm, a.partial, a.y, a.nrows, threadIdx.x & 63);
 }
 
-template <int COMBO, int C, int U>
+template <int COMBO, int C, int U, int VV>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t b = a.swizzle ? xcd_swizzle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
@@ -220,8 +264,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
   } else {
     item = (int32_t)w;
   }
-  spmv_unit<COMBO, C, U>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff, a.partial,
-                         a.seg_steps, lane);
+  spmv_unit<COMBO, C, U, VV>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff, a.partial,
+                             a.seg_cols, lane);
 }
 
 // Persistent batched form: wave w runs units [slice[w], slice[w+1]) of the
@@ -236,8 +280,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
     const BUnit u = a.units[q];
     const BatchMat m = a.mats[u.mat];
     const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
-    spmv_unit<COMBO, C, U>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg, poff,
-                           a.partial, a.seg_steps, lane);
+    spmv_unit<COMBO, C, U, 1>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg, poff,
+                              a.partial, a.seg_cols, lane);
   }
 }
 
@@ -312,8 +356,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   const int cl = a.cl[chunk];
   int jb = 0, je = cl;
   if (nseg > 1) {
-    jb = seg * a.seg_steps * G;
-    je = jb + a.seg_steps * G < cl ? jb + a.seg_steps * G : cl;
+    jb = seg * a.seg_cols;
+    je = jb + a.seg_cols < cl ? jb + a.seg_cols : cl;
   }
   const int32_t *cp = a.col + base + r;
   const double *vp = static_cast<const double *>(a.val) + base + r;
@@ -401,26 +445,33 @@ __global__ void __launch_bounds__(64) k_combine_mm(SpmvArgs a) {
 namespace sell {
 namespace dev {
 
-// Host-side launchers for one dtype combination; every supported (C, U)
-// pair is instantiated.
+// Host-side launchers for one dtype combination; every supported
+// (C, U, VV) is instantiated. U*VV (slots in flight per lane) is 4 or 8.
+#define SELL_FOR_EACH_CUV(X)                                                                                         \
+  X(1, 4, 1) X(1, 8, 1) X(2, 4, 1) X(2, 8, 1) X(4, 4, 1) X(4, 8, 1) X(8, 4, 1) X(8, 8, 1) X(16, 4, 1) X(16, 8, 1) \
+      X(32, 4, 1) X(32, 8, 1) X(64, 4, 1) X(64, 8, 1) X(128, 4, 1) X(128, 8, 1) X(2, 2, 2) X(2, 4, 2) X(4, 2, 2)   \
+          X(4, 4, 2) X(8, 2, 2) X(8, 4, 2) X(16, 2, 2) X(16, 4, 2) X(32, 2, 2) X(32, 4, 2) X(64, 2, 2) X(64, 4, 2) \
+              X(4, 1, 4) X(4, 2, 4) X(8, 1, 4) X(8, 2, 4) X(16, 1, 4) X(16, 2, 4) X(32, 1, 4) X(32, 2, 4)          \
+                  X(64, 1, 4) X(64, 2, 4)
+
 #define SELL_FOR_EACH_CU(X) \
   X(1, 4) X(1, 8) X(2, 4) X(2, 8) X(4, 4) X(4, 8) X(8, 4) X(8, 8) X(16, 4) X(16, 8) X(32, 4) X(32, 8) X(64, 4) \
       X(64, 8) X(128, 4) X(128, 8)
 
 template <int COMBO>
-hipError_t launch_spmv_t(int C, int U, const SpmvArgs &a, hipStream_t s) {
+hipError_t launch_spmv_t(int C, int U, int VV, const SpmvArgs &a, hipStream_t s) {
   if (a.nwork <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((a.nwork + kWavesPerBlock - 1) / kWavesPerBlock);
-#define SELL_L(CC, UU)                                                                                      \
-  if (C == CC && U == UU) {                                                                                \
-    hipLaunchKernelGGL((k_spmv<COMBO, CC, UU>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);            \
-    hipError_t e_ = hipGetLastError();                                                                     \
-    if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                      \
-    const unsigned nbc = (unsigned)((a.nsplit + kWavesPerBlock - 1) / kWavesPerBlock);                      \
-    hipLaunchKernelGGL((k_combine<COMBO, CC>), dim3(nbc), dim3(64 * kWavesPerBlock), 0, s, a);             \
-    return hipGetLastError();                                                                              \
+#define SELL_L(CC, UU, VVV)                                                                                  \
+  if (C == CC && U == UU && VV == VVV) {                                                                    \
+    hipLaunchKernelGGL((k_spmv<COMBO, CC, UU, VVV>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);         \
+    hipError_t e_ = hipGetLastError();                                                                       \
+    if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                        \
+    const unsigned nbc = (unsigned)((a.nsplit + kWavesPerBlock - 1) / kWavesPerBlock);                        \
+    hipLaunchKernelGGL((k_combine<COMBO, CC>), dim3(nbc), dim3(64 * kWavesPerBlock), 0, s, a);               \
+    return hipGetLastError();                                                                                \
   }
-  SELL_FOR_EACH_CU(SELL_L)
+  SELL_FOR_EACH_CUV(SELL_L)
 #undef SELL_L
   return hipErrorInvalidValue;
 }

@@ -40,15 +40,15 @@ class SellAllocator(ctypes.Structure):
 
 
 class SellBuildOpts(ctypes.Structure):
-    _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("seg_steps", c_i32),
-                ("ktile", c_i32), ("kmax", c_i32), ("alloc", ctypes.POINTER(SellAllocator))]
+    _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("vec", c_i32),
+                ("seg_cols", c_i32), ("ktile", c_i32), ("kmax", c_i32), ("alloc", ctypes.POINTER(SellAllocator))]
 
 
 class SellInfo(ctypes.Structure):
     _fields_ = [("nrows", c_i64), ("ncols", c_i64), ("nnz", c_i64), ("C", c_i32), ("sigma", c_i64),
                 ("nchunks", c_i64), ("padded", c_i64), ("beta", c_d), ("zeta", c_d), ("max_row_len", c_i64),
                 ("val_dtype", ctypes.c_int), ("x_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int),
-                ("lanes_per_row", c_i32), ("unroll", c_i32), ("seg_steps", c_i32), ("nunits", c_i64),
+                ("lanes_per_row", c_i32), ("unroll", c_i32), ("vec", c_i32), ("seg_cols", c_i32), ("nunits", c_i64),
                 ("nsplit", c_i64), ("has_perm", c_i32), ("device_bytes", c_i64)]
 
 
@@ -162,16 +162,17 @@ class SellMatrix:
             self._h = None
 
     def __del__(self):
-        if getattr(self, "_h", None) and not sys.is_finalizing():
-            try:
+        try:
+            if getattr(self, "_h", None) and not sys.is_finalizing():
                 lib().sell_destroy(self._h)
-            except Exception:
-                pass
-            self._h = None
+        except Exception:
+            pass
+        self._h = None
 
 
 def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
-               unroll: int = 0, seg_steps: int = 0, ktile: int = 0, kmax: int = 0, stream=None) -> SellMatrix:
+               unroll: int = 0, vec: int = 0, seg_cols: int = 0, ktile: int = 0, kmax: int = 0,
+               stream=None) -> SellMatrix:
     """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64)."""
     import torch
     nrows = rpt.numel() - 1
@@ -180,7 +181,7 @@ def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "
                 _dptr(val, torch.float64, "val", nnz))
     if acc_dtype is None:
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
-    o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, seg_steps, ktile, kmax, None)
+    o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax, None)
     h = c_p()
     _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
     return SellMatrix(h)
@@ -242,12 +243,12 @@ class SellBatch:
             self._h = None
 
     def __del__(self):
-        if getattr(self, "_h", None) and not sys.is_finalizing():
-            try:
+        try:
+            if getattr(self, "_h", None) and not sys.is_finalizing():
                 lib().sell_batch_destroy(self._h)
-            except Exception:
-                pass
-            self._h = None
+        except Exception:
+            pass
+        self._h = None
 
 
 def sell_batch_create(mats) -> SellBatch:

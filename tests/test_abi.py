@@ -66,11 +66,15 @@ def test_host_side_argument_errors(L):
     assert L.sell_build(ctypes.byref(Aneg), 32, 1, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
     Abig = sellcs.SellCrs(2**31, 10, 0, ctypes.c_void_p(8), None, None)
     assert L.sell_build(ctypes.byref(Abig), 32, 1, None, None, ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
-    f64_val_f32_acc = sellcs.SellBuildOpts(0, 1, 0, 0, 0, 0, None)  # FP64 values need FP64 accumulation
+    f64_val_f32_acc = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=1)  # FP64 values need FP64 accumulation
     assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(f64_val_f32_acc), None,
                         ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
-    badu = sellcs.SellBuildOpts(0, 0, 5, 0, 0, 0, None)
+    badu = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, unroll=5)
     assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badu), None, ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    for C, vec in [(128, 2), (2, 4), (32, 3)]:
+        badv = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, vec=vec)
+        assert L.sell_build(ctypes.byref(A), C, 1, ctypes.byref(badv), None,
+                            ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
     assert L.sell_spmv(None, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmmv(None, None, None, 4, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_batch_create(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG

@@ -59,7 +59,7 @@ def test_info_fields():
     h = build(A, 32, 64)
     inf = h.info
     assert inf["nrows"] == A.nrows and inf["nnz"] == A.nnz and inf["C"] == 32 and inf["sigma"] == 64
-    assert inf["has_perm"] == 1 and inf["lanes_per_row"] == 2
+    assert inf["has_perm"] == 1 and inf["lanes_per_row"] == 64 * inf["vec"] // 32
     assert inf["max_row_len"] == int(A.row_lengths().max())
     L = A.row_lengths().astype(np.float64)
     assert abs(inf["zeta"] - L.std() / L.mean()) < 1e-9

@@ -32,7 +32,7 @@ def test_spmmv(k, C, sigma):
     A = synth.powerlaw(30_000, seed=41)
     X = synth.block_vector(A.ncols, k, seed=42)
     say("spmmv k", k, "C", C, "sigma", sigma)
-    h = build(A, C, sigma, seg_steps=-1)
+    h = build(A, C, sigma, seg_cols=-1)
     check(A, run_spmmv(h, X), X)
 
 
@@ -49,7 +49,7 @@ def test_spmmv_ktile(ktile):
 def test_spmmv_split(k, C):
     A = synth.powerlaw(30_000, seed=45)
     X = synth.block_vector(A.ncols, k, seed=46)
-    h = build(A, C, 1, seg_steps=3)
+    h = build(A, C, 1, seg_cols=64)
     assert h.info["nsplit"] > 0
     Y1 = run_spmmv(h, X)
     check(A, Y1, X)
@@ -59,7 +59,7 @@ def test_spmmv_split(k, C):
 def test_spmmv_k_above_kmax_rejected():
     from paper_1307_6209_amd import sellcs
     A = synth.powerlaw(30_000, seed=47)
-    h = build(A, 32, 1, seg_steps=3, kmax=8)
+    h = build(A, 32, 1, seg_cols=64, kmax=8)
     with pytest.raises(sellcs.SellError):
         run_spmmv(h, synth.block_vector(A.ncols, 16))
     check(A, run_spmmv(h, synth.block_vector(A.ncols, 8)), synth.block_vector(A.ncols, 8))

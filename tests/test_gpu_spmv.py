@@ -23,25 +23,27 @@ CS = [(1, 1), (2, 1), (4, 7), (8, 1), (16, 1), (16, 256), (32, 1), (32, 10**9), 
 
 @pytest.mark.parametrize("name", list(MATS))
 @pytest.mark.parametrize("C,sigma", CS)
-@pytest.mark.parametrize("unroll", [4, 8])
-def test_spmv_fp64(name, C, sigma, unroll):
+@pytest.mark.parametrize("unroll,vec", [(4, 1), (8, 1), (4, 2), (8, 2), (4, 4), (8, 4), (0, 0)])
+def test_spmv_fp64(name, C, sigma, unroll, vec):
+    if vec > 1 and (C > 64 or vec > C):
+        pytest.skip("vec > 1 needs C <= 64 and vec <= C")
     A = MATS[name]()
     x = synth.uniform(A.ncols, 11, 1)
-    say("spmv", name, "C", C, "sigma", sigma, "U", unroll)
-    h = build(A, C, sigma, unroll=unroll)
+    say("spmv", name, "C", C, "sigma", sigma, "U", unroll, "V", vec)
+    h = build(A, C, sigma, unroll=unroll, vec=vec)
     y = spmv_gpu(h, x)
     check_fp64(A, y, x)
 
 
-@pytest.mark.parametrize("seg", [1, 2, 7, 64])
-@pytest.mark.parametrize("C", [1, 8, 32, 128])
-def test_split_chunks(seg, C):
-    """Chunks cut into segments of `seg` wave steps: partial sums combined
-    by the last segment; identical bits on repeated calls."""
+@pytest.mark.parametrize("seg", [64, 128, 448, 4096])
+@pytest.mark.parametrize("C,vec", [(1, 1), (8, 1), (8, 4), (32, 1), (32, 2), (64, 4), (128, 1)])
+def test_split_chunks(seg, C, vec):
+    """Chunks cut into segments of `seg` chunk columns: segment sums added in
+    order by the combining kernel; identical bits on repeated calls."""
     A = synth.powerlaw(40_000, seed=8)
     x = synth.uniform(A.ncols, 12, 1)
-    say("split", "C", C, "seg", seg)
-    h = build(A, C, 1, seg_steps=seg)
+    say("split", "C", C, "seg", seg, "V", vec)
+    h = build(A, C, 1, seg_cols=seg, vec=vec)
     assert h.info["nsplit"] > 0
     y1 = spmv_gpu(h, x)
     check_fp64(A, y1, x)
@@ -53,7 +55,7 @@ def test_auto_split_on_long_rows():
     A = synth.powerlaw(200_000, seed=9)
     h = build(A, 32, 1)
     inf = h.info
-    say("auto split", inf["seg_steps"], inf["nsplit"], inf["nunits"])
+    say("auto split", inf["seg_cols"], inf["nsplit"], inf["nunits"])
     x = synth.uniform(A.ncols, 13, 1)
     check_fp64(A, spmv_gpu(h, x), x)
 
