@@ -146,7 +146,35 @@ def run_forms(args) -> dict:
         t = time_calls(lambda: sellcs.sell_spmv(h, x, y), max(20, args.steps // 5), 5)
         pl["C%d_sigma%d" % (C, s)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(h.info["beta"], 4)}
         h.close()
+    hs_ = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, permute_columns=True)
+    xp = torch.empty_like(x)
+    sellcs.sell_permute(hs_, x, xp)
+    t = time_calls(lambda: sellcs.sell_spmv(hs_, xp, y), max(20, args.steps // 5), 5)
+    pl["C32_sigma%d_symmetric" % A.nrows] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(hs_.info["beta"], 4)}
+    hs_.close()
+    for L in (1, 4):
+        t = time_calls(lambda: sellcs.sell_crs_spmv(r, c, v, x, y, A.ncols, lanes_per_row=L), max(20, args.steps // 5), 5)
+        pl["crs_L%d" % L] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2)}
     out["powerlaw_2m"] = pl
+    del r, c, v
+    # few rows, long rows: dense 8000^2 and a rail4284-shaped matrix (Sect. 5.2)
+    for name, Cs in (("dense_8000", (32, 128)), ("rail_like", (32, 128))):
+        B = synth.workload(name)
+        rr, cc, vv = to_dev(B)
+        xb = torch.from_numpy(synth.uniform(B.ncols)).cuda()
+        yb = torch.empty(B.nrows, dtype=torch.float64, device="cuda")
+        res = {}
+        for C in Cs:
+            for sg in (1, B.nrows):
+                hb = sellcs.sell_build(rr, cc, vv, B.ncols, C, sg)
+                t = time_calls(lambda: sellcs.sell_spmv(hb, xb, yb), max(20, args.steps // 10), 5)
+                res["C%d_sigma%d" % (C, sg)] = {"gfs": round(2.0 * B.nnz / t * 1e-9, 2), "beta": round(hb.info["beta"], 4)}
+                hb.close()
+        t = time_calls(lambda: sellcs.sell_crs_spmv(rr, cc, vv, xb, yb, B.ncols, lanes_per_row=64),
+                       max(20, args.steps // 10), 5)
+        res["crs_L64"] = {"gfs": round(2.0 * B.nnz / t * 1e-9, 2)}
+        out[name] = res
+        del rr, cc, vv
     return out
 
 
@@ -252,6 +280,15 @@ def main():
         forms["%s_val_%s_acc" % (vd, ad)] = round(2.0 * A.nnz / t * 1e-9, 2)
         hf.close()
     line["forms_stencil27_160_gfs"] = forms
+    # the paper's comparison on one device: CRS (one lane per row, and L lanes
+    # per row with a cross-lane reduction) against SELL-C-sigma
+    crs = {}
+    for L in (1, 4, 8, 16, 32):
+        t = time_calls(lambda: sellcs.sell_crs_spmv(r, c, v, x, y, A.ncols, lanes_per_row=L), max(50, args.steps // 4),
+                       10)
+        crs["crs_L%d" % L] = round(2.0 * A.nnz / t * 1e-9, 2)
+    crs["sell_%d_%d" % (HEADLINE["C"], HEADLINE["sigma"])] = round(gfs, 2)
+    line["crs_vs_sell_stencil27_160_gfs"] = crs
     h.close()
     del r, c, v
     if not args.no_forms:

@@ -81,6 +81,12 @@ typedef struct {
   int32_t kmax;         /* largest k sell_spmmv will be called with on matrices
                            whose chunks are split (sizes the partial-sum buffer):
                            0 means 32 */
+  int32_t permute_columns; /* 0: column ids stay the caller's (x, y in original
+                           order). 1: columns are renumbered with the row order
+                           too (square matrices only), i.e. the matrix stored is
+                           P A P^T and x, y live in sorted order -- the form the
+                           paper recommends for iterative solvers (Sect. 3.4);
+                           see sell_permute / sell_unpermute */
   const sell_allocator *alloc; /* NULL: hipMalloc/hipFree */
 } sell_build_opts;
 
@@ -101,6 +107,7 @@ typedef struct {
   int64_t nunits;        /* work units of one sell_spmv launch */
   int64_t nsplit;        /* row slices whose chunk is split over several waves */
   int32_t has_perm;      /* 0 when the row order is the identity (sigma == 1) */
+  int32_t permuted_columns; /* 1 when built with permute_columns */
   int64_t device_bytes;  /* device memory held by the handle */
 } sell_info_t;
 
@@ -197,6 +204,28 @@ sell_status sell_batch_spmv(sell_batch b, const void *const *xs,
                             void *const *ys, void *stream);
 
 sell_status sell_batch_destroy(sell_batch b);
+
+/*
+ * sell_permute -- xp[p] = x[perm[p]] for p < nrows: a vector in the caller's
+ * order to sorted order (square handles; x dtype of the handle).
+ * sell_unpermute -- y[perm[p]] = yp[p]: back to the caller's order
+ * (accumulation dtype). Both asynchronous on stream; in and out must not
+ * overlap. With permute_columns, sell_spmv maps a sorted-order x to a
+ * sorted-order y, so a solver can stay in sorted order and convert once.
+ */
+sell_status sell_permute(sell_handle h, const void *x, void *xp, void *stream);
+sell_status sell_unpermute(sell_handle h, const void *yp, void *y, void *stream);
+
+/*
+ * sell_crs_spmv -- y = A x straight from CRS (Sect. 3.1, Listing "CRS spMVM
+ * kernel"; y is overwritten), FP64, for comparison with SELL-C-sigma on the
+ * same device (Sects. 3.2, 5.1). lanes_per_row: 1 = one lane per row (scalar
+ * CRS), 2..64 = that many lanes walk a row and add their sums across lanes,
+ * 0 = chosen from the mean row length. The CRS arrays are not validated (use
+ * sell_build for that). Asynchronous on stream.
+ */
+sell_status sell_crs_spmv(const sell_crs *A, int32_t lanes_per_row, const double *x,
+                          double *y, void *stream);
 
 /* Autotuner search space (zero-length lists fall back to defaults). */
 typedef struct {

@@ -52,6 +52,8 @@ def _L():
         lib.or_sell_layout.argtypes = [i64, p, i32, i64, p, p, p]
         lib.or_sell_layout.restype = ctypes.c_int
         lib.or_sell_fill.argtypes = [i64, p, p, p, i32, p, p, p, p, p]
+        lib.or_crs_symperm.argtypes = [i64, p, p, p, p, p, p, p]
+        lib.or_crs_symperm.restype = ctypes.c_int
         lib.or_sell_beta.argtypes = [i64, i64]
         lib.or_sell_beta.restype = d
         lib.or_row_zeta.argtypes = [i64, p]
@@ -154,10 +156,35 @@ def sell_layout(A, C: int, sigma: int):
     return perm, cl, cs
 
 
-def sell_build(A, C: int, sigma: int, val_dtype: str = "f64") -> dict:
+def crs_symperm(A, perm):
+    """P A P^T: row p is row perm[p] of A with columns renamed by the inverse
+    permutation (square matrices)."""
+    if A.nrows != A.ncols:
+        raise ValueError("symmetric permutation needs a square matrix")
+    rpt, col, val = _arrays(A)
+    perm = _c(perm, np.int32)
+    rpt2 = np.empty(A.nrows + 1, np.int64)
+    col2 = np.empty(col.size, np.int32)
+    val2 = np.empty(col.size, np.float64)
+    rc = _L().or_crs_symperm(A.nrows, _p(rpt), _p(col), _p(val), _p(perm), _p(rpt2), _p(col2), _p(val2))
+    if rc != 0:
+        raise MemoryError("or_crs_symperm")
+    return type(A)(A.nrows, A.ncols, rpt2, col2, val2)
+
+
+def sell_build(A, C: int, sigma: int, val_dtype: str = "f64", permute_columns: bool = False) -> dict:
     """The full SELL-C-sigma representation of A as a dict of numpy arrays:
     perm, cl, cs, col, val (float64, or float32, or bfloat16 bits as uint16),
-    plus nchunks, padded, beta, zeta."""
+    plus nchunks, padded, beta, zeta. With permute_columns the stored matrix
+    is P A P^T in sorted row order (its own row order is the identity) and
+    perm is the sort of A."""
+    if permute_columns:
+        perm, _, _ = sell_layout(A, C, sigma)
+        S = sell_build(crs_symperm(A, perm), C, 1, val_dtype)
+        S["perm"] = perm
+        S["sigma"] = sigma
+        S["zeta"] = row_zeta(A)
+        return S
     perm, cl, cs = sell_layout(A, C, sigma)
     padded = int(cs[-1])
     scol = np.empty(padded, np.int32)

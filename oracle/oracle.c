@@ -222,6 +222,31 @@ void or_sell_fill(int64_t n, const int64_t *rpt, const int32_t *col,
       }
 }
 
+/*
+ * Symmetric permutation P A P^T of a square CRS matrix (Sect. 3.4: after the
+ * row sort, column indices are permuted accordingly so that an iterative
+ * solver can work in the permuted index space). Row p of the result is row
+ * perm[p] of A, entries in their CRS order, each column c renamed iperm[c]
+ * with iperm[perm[p]] = p. rpt2 has n + 1 entries, col2/val2 nnz.
+ */
+int or_crs_symperm(int64_t n, const int64_t *rpt, const int32_t *col, const double *val,
+                   const int32_t *perm, int64_t *rpt2, int32_t *col2, double *val2) {
+  int32_t *iperm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!iperm) return -1;
+  for (int64_t p = 0; p < n; ++p) iperm[perm[p]] = (int32_t)p;
+  rpt2[0] = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t row = perm[p], k = rpt2[p];
+    for (int64_t j = rpt[row]; j < rpt[row + 1]; ++j, ++k) {
+      col2[k] = iperm[col[j]];
+      val2[k] = val[j];
+    }
+    rpt2[p + 1] = k;
+  }
+  free(iperm);
+  return 0;
+}
+
 /* Chunk occupancy, Eq. (beta): nnz over the stored slots. */
 double or_sell_beta(int64_t nnz, int64_t padded) {
   return padded == 0 ? 1.0 : (double)nnz / (double)padded;

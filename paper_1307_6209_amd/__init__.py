@@ -8,5 +8,5 @@ sparse matrix-vector multiply on modern processors with wide SIMD units"
 paper's code-balance performance model.
 """
 from .sellcs import (SellBatch, SellError, SellMatrix, sell_autotune, sell_batch_create,  # noqa: F401
-                     sell_batch_destroy, sell_batch_spmv, sell_build, sell_destroy, sell_export, sell_info,
-                     sell_probe_bandwidth, sell_spmmv, sell_spmv)
+                     sell_batch_destroy, sell_batch_spmv, sell_build, sell_crs_spmv, sell_destroy, sell_export,
+                     sell_info, sell_permute, sell_probe_bandwidth, sell_spmmv, sell_spmv, sell_unpermute)

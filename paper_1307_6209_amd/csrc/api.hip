@@ -201,6 +201,8 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
   if (o.ktile < 0 || o.ktile > 64 || (o.ktile & (o.ktile - 1)) != 0)
     return fail(SELL_ERR_UNSUPPORTED, "sell_build: ktile must be 0 or a power of two <= 64");
   if (o.kmax < 0) return fail(SELL_ERR_INVALID_ARG, "sell_build: kmax must be >= 0");
+  if (o.permute_columns && A->nrows != A->ncols)
+    return fail(SELL_ERR_UNSUPPORTED, "sell_build: permute_columns needs a square matrix");
   if (o.alloc && (!o.alloc->alloc || !o.alloc->free))
     return fail(SELL_ERR_INVALID_ARG, "sell_build: allocator needs alloc and free");
 
@@ -219,6 +221,7 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
   h->unroll = o.unroll ? o.unroll : 8;
   h->ktile = o.ktile;
   h->kmax = o.kmax ? o.kmax : 32;
+  h->sym = o.permute_columns != 0;
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   Mem mem;
   if (o.alloc) {
@@ -303,8 +306,14 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
     h->col = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * (size_t)h->padded));
     h->val = owned_alloc(h.get(), mem, dtype_size(h->vdt) * (size_t)h->padded);
     if (!h->col || !h->val) return fail(SELL_ERR_OOM, "sell_build: padded arrays");
-    SELL_HIP(sell::build_fill(A->rpt, A->col, A->val, n, C, h->perm, len, h->cs, nc, h->padded, h->col, h->val,
-                              (int)h->vdt, s));
+    int32_t *iperm = nullptr;
+    if (h->sym && h->perm) {
+      iperm = static_cast<int32_t *>(tmp.get(sizeof(int32_t) * (size_t)n));
+      if (!iperm) return fail(SELL_ERR_OOM, "sell_build: inverse permutation");
+      SELL_HIP(sell::build_invert(h->perm, n, iperm, s));
+    }
+    SELL_HIP(sell::build_fill(A->rpt, A->col, A->val, n, C, h->perm, len, h->cs, nc, h->padded, iperm, h->col,
+                              h->val, (int)h->vdt, s));
   }
 
   // host copy of the chunk widths, then the work plan
@@ -365,7 +374,7 @@ sell::SpmvArgs args_of(const sell_matrix *h, const void *x, void *y) {
   a.col = h->col;
   a.cs = h->cs;
   a.cl = h->cl;
-  a.perm = h->perm;
+  a.perm = h->sym ? nullptr : h->perm;  // symmetric mode: y is written in sorted order
   a.x = x;
   a.y = y;
   a.nrows = h->nrows;
@@ -458,6 +467,7 @@ extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
   r.nunits = h->units ? h->nunits : h->nitems;
   r.nsplit = h->nsplit;
   r.has_perm = h->perm ? 1 : 0;
+  r.permuted_columns = h->sym ? 1 : 0;
   r.device_bytes = h->device_bytes;
   *info = r;
   return SELL_OK;
@@ -631,7 +641,7 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
     m.col = hs[b]->col;
     m.cs = hs[b]->cs;
     m.cl = hs[b]->cl;
-    m.perm = hs[b]->perm;
+    m.perm = hs[b]->sym ? nullptr : hs[b]->perm;
     m.x = nullptr;
     m.y = nullptr;
     m.nrows = hs[b]->nrows;
@@ -691,6 +701,44 @@ extern "C" sell_status sell_batch_destroy(sell_batch b) {
   (void)hipDeviceSynchronize();
   batch_free(b);
   delete b;
+  return SELL_OK;
+}
+
+// ===========================================================================
+// Sorted-order helpers and the CRS comparison kernels
+// ===========================================================================
+extern "C" sell_status sell_permute(sell_handle h, const void *x, void *xp, void *stream) {
+  if (!h || ((!x || !xp) && h->nrows > 0)) return fail(SELL_ERR_INVALID_ARG, "sell_permute: null argument");
+  if (h->nrows != h->ncols) return fail(SELL_ERR_UNSUPPORTED, "sell_permute: square matrices only");
+  hipError_t e = sell::permute_vector(x, xp, h->perm, h->nrows, (int)dtype_size(h->xdt), false,
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail("sell_permute", e);
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_unpermute(sell_handle h, const void *yp, void *y, void *stream) {
+  if (!h || ((!y || !yp) && h->nrows > 0)) return fail(SELL_ERR_INVALID_ARG, "sell_unpermute: null argument");
+  hipError_t e = sell::permute_vector(yp, y, h->perm, h->nrows, (int)dtype_size(h->adt), true,
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail("sell_unpermute", e);
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_crs_spmv(const sell_crs *A, int32_t lanes_per_row, const double *x, double *y,
+                                     void *stream) {
+  if (!A || (A->nrows > 0 && (!A->rpt || !y)) || (A->nnz > 0 && (!A->col || !A->val || !x)))
+    return fail(SELL_ERR_INVALID_ARG, "sell_crs_spmv: null argument");
+  if (A->nrows < 0) return fail(SELL_ERR_INVALID_ARG, "sell_crs_spmv: negative size");
+  int L = lanes_per_row;
+  if (L == 0) {  // about half a wave step per row: the row length rounded down to a power of two
+    double nnzr = A->nrows > 0 ? (double)A->nnz / (double)A->nrows : 1.0;
+    L = 1;
+    while (L < 64 && 2.0 * L <= nnzr) L *= 2;
+  }
+  if (L < 1 || L > 64 || (L & (L - 1)) != 0)
+    return fail(SELL_ERR_UNSUPPORTED, "sell_crs_spmv: lanes_per_row must be 0 or a power of two <= 64");
+  hipError_t e = sell::launch_crs(A->rpt, A->col, A->val, x, y, A->nrows, L, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail("sell_crs_spmv", e);
   return SELL_OK;
 }
 

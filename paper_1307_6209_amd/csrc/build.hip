@@ -320,7 +320,8 @@ __global__ void __launch_bounds__(kBlock) k_fill(const int64_t *__restrict__ rpt
                                                  const double *__restrict__ val, int64_t n, int C,
                                                  const int32_t *__restrict__ perm, const int32_t *__restrict__ len,
                                                  const int64_t *__restrict__ cs, int64_t nchunks, int64_t padded,
-                                                 int32_t *__restrict__ scol, void *__restrict__ sval) {
+                                                 const int32_t *__restrict__ cmap, int32_t *__restrict__ scol,
+                                                 void *__restrict__ sval) {
   int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < padded; s += stride) {
     // largest i with cs[i] <= s
@@ -340,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_fill(const int64_t *__restrict__ rpt
       int64_t row = perm ? perm[p] : p;
       if (j < len[row]) {
         int64_t src = rpt[row] + j;
-        c = col[src];
+        c = cmap ? cmap[col[src]] : col[src];
         v = val[src];
       }
     }
@@ -351,9 +352,56 @@ __global__ void __launch_bounds__(kBlock) k_fill(const int64_t *__restrict__ rpt
   }
 }
 
+// iperm[perm[p]] = p
+__global__ void __launch_bounds__(kBlock) k_invert(const int32_t *__restrict__ perm, int64_t n,
+                                                   int32_t *__restrict__ iperm) {
+  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p < n) iperm[perm[p]] = (int32_t)p;
+}
+
+// out[p] = in[perm[p]] (gather into sorted order) or out[perm[p]] = in[p]
+// (scatter back), for elements of ES bytes.
+template <typename E, bool SCATTER>
+__global__ void __launch_bounds__(kBlock) k_permute(const E *__restrict__ in, E *__restrict__ out,
+                                                    const int32_t *__restrict__ perm, int64_t n) {
+  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const int64_t q = perm ? (int64_t)perm[p] : p;
+  if (SCATTER) out[q] = in[p];
+  else out[p] = in[q];
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+hipError_t build_invert(const int32_t *perm, int64_t n, int32_t *iperm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_invert, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, perm, n, iperm);
+  return hipGetLastError();
+}
+
+hipError_t permute_vector(const void *in, void *out, const int32_t *perm, int64_t n, int elem_bytes, bool scatter,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(n, kBlock);
+  if (elem_bytes == 8) {
+    if (scatter)
+      hipLaunchKernelGGL((k_permute<uint64_t, true>), dim3(nb), dim3(kBlock), 0, s, static_cast<const uint64_t *>(in),
+                         static_cast<uint64_t *>(out), perm, n);
+    else
+      hipLaunchKernelGGL((k_permute<uint64_t, false>), dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const uint64_t *>(in), static_cast<uint64_t *>(out), perm, n);
+  } else {
+    if (scatter)
+      hipLaunchKernelGGL((k_permute<uint32_t, true>), dim3(nb), dim3(kBlock), 0, s, static_cast<const uint32_t *>(in),
+                         static_cast<uint32_t *>(out), perm, n);
+    else
+      hipLaunchKernelGGL((k_permute<uint32_t, false>), dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const uint32_t *>(in), static_cast<uint32_t *>(out), perm, n);
+  }
+  return hipGetLastError();
+}
 
 hipError_t build_rowlen(const int64_t *rpt, int64_t n, int64_t nnz, int32_t *len, uint32_t *flags,
                         unsigned long long *sumsq, int32_t *maxlen, hipStream_t s) {
@@ -430,19 +478,19 @@ hipError_t build_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, 
 
 hipError_t build_fill(const int64_t *rpt, const int32_t *col, const double *val, int64_t n, int C,
                       const int32_t *perm, const int32_t *len, const int64_t *cs, int64_t nchunks, int64_t padded,
-                      int32_t *scol, void *sval, int val_dtype, hipStream_t s) {
+                      const int32_t *cmap, int32_t *scol, void *sval, int val_dtype, hipStream_t s) {
   if (padded <= 0) return hipSuccess;
   int64_t nb = blocks_for(padded, kBlock);
   if (nb > 262144) nb = 262144;
   if (val_dtype == SELL_F64)
     hipLaunchKernelGGL(k_fill<SELL_F64>, dim3((unsigned)nb), dim3(kBlock), 0, s, rpt, col, val, n, C, perm, len, cs,
-                       nchunks, padded, scol, sval);
+                       nchunks, padded, cmap, scol, sval);
   else if (val_dtype == SELL_F32)
     hipLaunchKernelGGL(k_fill<SELL_F32>, dim3((unsigned)nb), dim3(kBlock), 0, s, rpt, col, val, n, C, perm, len, cs,
-                       nchunks, padded, scol, sval);
+                       nchunks, padded, cmap, scol, sval);
   else
     hipLaunchKernelGGL(k_fill<SELL_BF16>, dim3((unsigned)nb), dim3(kBlock), 0, s, rpt, col, val, n, C, perm, len,
-                       cs, nchunks, padded, scol, sval);
+                       cs, nchunks, padded, cmap, scol, sval);
   return hipGetLastError();
 }
 

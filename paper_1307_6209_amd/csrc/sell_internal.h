@@ -150,9 +150,17 @@ hipError_t build_chunkwidth(const int32_t *len, const int32_t *perm, int64_t n, 
 // Exclusive scan of n int64 values (in-place allowed); tmp needs scan_tmp_elems(n) int64.
 int64_t scan_tmp_elems(int64_t n);
 hipError_t build_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+// cmap: column map applied to every stored column index (nullptr: none).
 hipError_t build_fill(const int64_t *rpt, const int32_t *col, const double *val, int64_t n, int C,
                       const int32_t *perm, const int32_t *len, const int64_t *cs, int64_t nchunks,
-                      int64_t padded, int32_t *scol, void *sval, int val_dtype, hipStream_t s);
+                      int64_t padded, const int32_t *cmap, int32_t *scol, void *sval, int val_dtype,
+                      hipStream_t s);
+hipError_t build_invert(const int32_t *perm, int64_t n, int32_t *iperm, hipStream_t s);
+// out[p] = in[perm[p]] (scatter = false) or out[perm[p]] = in[p] (scatter = true).
+hipError_t permute_vector(const void *in, void *out, const int32_t *perm, int64_t n, int elem_bytes, bool scatter,
+                          hipStream_t s);
+hipError_t launch_crs(const int64_t *rpt, const int32_t *col, const double *val, const double *x, double *y,
+                      int64_t n, int L, hipStream_t s);
 
 // Bandwidth probes.
 hipError_t probe_read(const void *a, size_t bytes, double *sink, hipStream_t s);
@@ -175,6 +183,7 @@ struct sell_matrix {
   int32_t seg_cols = 0;
   int32_t ktile = 0;
   int32_t kmax = 32;
+  bool sym = false;  // column indices permuted too: x and y live in sorted order
   int device = 0;
 
   int32_t *perm = nullptr;

@@ -41,7 +41,8 @@ class SellAllocator(ctypes.Structure):
 
 class SellBuildOpts(ctypes.Structure):
     _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("vec", c_i32),
-                ("seg_cols", c_i32), ("ktile", c_i32), ("kmax", c_i32), ("alloc", ctypes.POINTER(SellAllocator))]
+                ("seg_cols", c_i32), ("ktile", c_i32), ("kmax", c_i32), ("permute_columns", c_i32),
+                ("alloc", ctypes.POINTER(SellAllocator))]
 
 
 class SellInfo(ctypes.Structure):
@@ -49,7 +50,7 @@ class SellInfo(ctypes.Structure):
                 ("nchunks", c_i64), ("padded", c_i64), ("beta", c_d), ("zeta", c_d), ("max_row_len", c_i64),
                 ("val_dtype", ctypes.c_int), ("x_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int),
                 ("lanes_per_row", c_i32), ("unroll", c_i32), ("vec", c_i32), ("seg_cols", c_i32), ("nunits", c_i64),
-                ("nsplit", c_i64), ("has_perm", c_i32), ("device_bytes", c_i64)]
+                ("nsplit", c_i64), ("has_perm", c_i32), ("permuted_columns", c_i32), ("device_bytes", c_i64)]
 
 
 class SellTuneSpace(ctypes.Structure):
@@ -78,6 +79,9 @@ SIGNATURES = {
     "sell_autotune": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, ctypes.POINTER(SellTuneSpace), c_p,
                                      ctypes.POINTER(SellTuned)]),
     "sell_probe_bandwidth": (ctypes.c_int, [c_i32, ctypes.c_size_t, c_i32, c_p, ctypes.POINTER(c_d)]),
+    "sell_permute": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
+    "sell_unpermute": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
+    "sell_crs_spmv": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, c_p, c_p, c_p]),
     "sell_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sell_last_error": (ctypes.c_char_p, []),
 }
@@ -172,7 +176,7 @@ class SellMatrix:
 
 def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
                unroll: int = 0, vec: int = 0, seg_cols: int = 0, ktile: int = 0, kmax: int = 0,
-               stream=None) -> SellMatrix:
+               permute_columns: bool = False, stream=None) -> SellMatrix:
     """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64)."""
     import torch
     nrows = rpt.numel() - 1
@@ -181,7 +185,8 @@ def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "
                 _dptr(val, torch.float64, "val", nnz))
     if acc_dtype is None:
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
-    o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax, None)
+    o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax,
+                      1 if permute_columns else 0, None)
     h = c_p()
     _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
     return SellMatrix(h)
@@ -226,6 +231,34 @@ def sell_export(h: SellMatrix) -> dict:
     p = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
     _check(lib().sell_export(h.handle, p(perm), p(cl), p(cs), p(col), p(val)), "sell_export")
     return dict(perm=perm, cl=cl, cs=cs, col=col, val=val)
+
+
+def sell_permute(h: SellMatrix, x, xp, stream=None):
+    """xp[p] = x[perm[p]]: caller's order -> sorted order."""
+    n = h.info["nrows"]
+    _check(lib().sell_permute(h.handle, _dptr(x, h.x_dtype, "x", n), _dptr(xp, h.x_dtype, "xp", n), _stream(stream)),
+           "sell_permute")
+    return xp
+
+
+def sell_unpermute(h: SellMatrix, yp, y, stream=None):
+    """y[perm[p]] = yp[p]: sorted order -> caller's order."""
+    n = h.info["nrows"]
+    _check(lib().sell_unpermute(h.handle, _dptr(yp, h.y_dtype, "yp", n), _dptr(y, h.y_dtype, "y", n),
+                                _stream(stream)), "sell_unpermute")
+    return y
+
+
+def sell_crs_spmv(rpt, col, val, x, y, ncols: int, lanes_per_row: int = 0, stream=None):
+    """y = A x straight from device CRS (FP64), the comparison kernel."""
+    import torch
+    nrows = rpt.numel() - 1
+    nnz = col.numel()
+    A = SellCrs(nrows, int(ncols), nnz, _dptr(rpt, torch.int64, "rpt"), _dptr(col, torch.int32, "col"),
+                _dptr(val, torch.float64, "val", nnz))
+    _check(lib().sell_crs_spmv(ctypes.byref(A), lanes_per_row, _dptr(x, torch.float64, "x", int(ncols)),
+                               _dptr(y, torch.float64, "y", nrows), _stream(stream)), "sell_crs_spmv")
+    return y
 
 
 def sell_destroy(h: SellMatrix):

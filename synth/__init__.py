@@ -59,6 +59,8 @@ def _L():
         lib.synth_powerlaw_lengths.argtypes = [i64, u64, d, i64, i64, p]
         lib.synth_powerlaw_fill.argtypes = [i64, u64, i64, p, p, p]
         lib.synth_powerlaw_fill.restype = ctypes.c_int
+        lib.synth_uniform_fill.argtypes = [i64, i64, u64, p, p, p]
+        lib.synth_uniform_fill.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -206,6 +208,28 @@ def worst_case_beta(C: int, nchunks: int) -> CRS:
     return CRS(n, n, rpt, col, val, name="worstbeta_C%d_x%d" % (C, nchunks))
 
 
+def rail_like(nrows: int = 4284, ncols: int = 1_092_610, mean_len: float = 2633.0, zeta: float = 1.6,
+              seed: int = SEED_STRUCT + 5) -> CRS:
+    """Few rows, very many columns (the shape of an LP constraint matrix such
+    as the paper's rail4284): row lengths lognormal with the given mean and
+    coefficient of variation zeta (capped at ncols/2, at least 1), columns
+    uniform without repetition, values N(0,1)."""
+    s2 = math.log(1.0 + zeta * zeta)
+    mu = math.log(mean_len) - s2 / 2.0
+    u1 = 1.0 - uniform(nrows, seed, 20, 0.0, 1.0)
+    u2 = uniform(nrows, seed, 21, 0.0, 1.0)
+    g = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    lens = np.clip(np.round(np.exp(mu + math.sqrt(s2) * g)), 1, ncols // 2).astype(np.int64)
+    rpt = np.zeros(nrows + 1, np.int64)
+    np.cumsum(lens, out=rpt[1:])
+    nnz = int(rpt[-1])
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz, np.float64)
+    if _L().synth_uniform_fill(nrows, ncols, seed, _ptr(rpt), _ptr(col), _ptr(val)) != 0:
+        raise RuntimeError("rail_like generator could not place distinct columns")
+    return CRS(nrows, ncols, rpt, col, val, name="rail_like_%dx%d" % (nrows, ncols))
+
+
 def dense(nrows: int, ncols: int, seed: int = SEED_VAL) -> CRS:
     """Fully populated nrows x ncols matrix in CRS, values U[-1,1)."""
     rpt = np.arange(nrows + 1, dtype=np.int64) * ncols
@@ -231,6 +255,10 @@ def workload(name: str):
         return stencil27(160, seed=SEED_VAL + 2)
     if name == "powerlaw_1m":
         return powerlaw(1_000_000, seed=SEED_STRUCT + 3)
+    if name == "dense_8000":
+        return dense(8000, 8000, seed=SEED_VAL + 5)
+    if name == "rail_like":
+        return rail_like()
     raise KeyError(name)
 
 

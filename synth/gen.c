@@ -208,3 +208,39 @@ int synth_powerlaw_fill(int64_t n, uint64_t seed, int64_t band,
   free(stamp);
   return 0;
 }
+
+/*
+ * Rectangular nrows x ncols matrix with given row pointers: every row draws
+ * its columns uniformly from [0, ncols) without repetition (stream 7,
+ * indexed by CRS position and attempt), sorted ascending; values N(0,1)
+ * (streams 8 and 9). Rows must be no longer than ncols / 2.
+ */
+int synth_uniform_fill(int64_t nrows, int64_t ncols, uint64_t seed, const int64_t *rpt,
+                       int32_t *col, double *val) {
+  uint64_t kc = stream_key(seed, 7), kv1 = stream_key(seed, 8), kv2 = stream_key(seed, 9);
+  int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncols > 0 ? ncols : 1));
+  if (!stamp) return -1;
+  for (int64_t c = 0; c < ncols; ++c) stamp[c] = -1;
+  for (int64_t i = 0; i < nrows; ++i) {
+    for (int64_t g = rpt[i]; g < rpt[i + 1]; ++g) {
+      int64_t c = -1;
+      for (uint64_t att = 0; att < 65536; ++att) {
+        c = (int64_t)(u01(draw(kc, ((uint64_t)g << 16) | att)) * (double)ncols);
+        if (c >= ncols) c = ncols - 1;
+        if (stamp[c] != i) break;
+        c = -1;
+      }
+      if (c < 0) { free(stamp); return -1; }
+      stamp[c] = i;
+      col[g] = (int32_t)c;
+    }
+    qsort(col + rpt[i], (size_t)(rpt[i + 1] - rpt[i]), sizeof(int32_t), cmp_i32);
+    for (int64_t g = rpt[i]; g < rpt[i + 1]; ++g) {
+      double u1 = 1.0 - u01(draw(kv1, (uint64_t)g));
+      double u2 = u01(draw(kv2, (uint64_t)g));
+      val[g] = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+    }
+  }
+  free(stamp);
+  return 0;
+}

@@ -185,3 +185,19 @@ def test_zeta_closed_form():
     assert abs(oracle.row_zeta(A) - 0.5) < 1e-15
     assert oracle.row_zeta(synth.stencil27(3, ones=True)) > 0
     assert oracle.row_zeta(synth.dense(10, 10)) == 0.0
+
+
+@pytest.mark.parametrize("sigma", [1, 4, 100, 10**9])
+def test_symmetric_permutation_identity(sigma):
+    """(P A P^T)(P x) = P (A x): the permuted matrix applied to the permuted
+    vector gives the permuted product, term for term in the same order."""
+    A = synth.powerlaw(3000, seed=33)
+    x = synth.uniform(A.ncols, 33, 1)
+    perm, _, _ = oracle.sell_layout(A, 8, sigma)
+    B = oracle.crs_symperm(A, perm)
+    assert np.array_equal(oracle.crs_spmv(B, x[perm]), oracle.crs_spmv(A, x)[perm])
+    S = oracle.sell_build(A, 8, sigma, permute_columns=True)
+    D = oracle.sell_build(A, 8, sigma)
+    assert np.array_equal(S["cs"], D["cs"]) and np.array_equal(S["perm"], D["perm"])
+    assert np.array_equal(oracle.sell_spmv(dict(S, perm=np.arange(A.nrows, dtype=np.int32)), A.nrows, x[perm]),
+                          oracle.crs_spmv(A, x)[perm])

@@ -62,3 +62,13 @@ def test_batch_sizes_range():
     s = synth.batch_sizes(1000)
     assert s.min() >= 1000 and s.max() < 200_000
     assert abs(np.log(s).mean() - (np.log(1e3) + np.log(2e5)) / 2) < 0.15
+
+
+def test_rail_like_shape():
+    R = synth.rail_like(nrows=600, ncols=200_000, mean_len=800, zeta=1.6, seed=3)
+    L = R.row_lengths()
+    assert R.nrows == 600 and R.ncols == 200_000
+    assert 0.8 < L.mean() / 800 < 1.2 and 1.0 < L.std() / L.mean() < 2.2
+    for i in range(0, 600, 50):
+        c = R.col[R.rpt[i]:R.rpt[i + 1]]
+        assert np.all(np.diff(c) > 0) and c.min() >= 0 and c.max() < 200_000
