@@ -195,6 +195,42 @@ def model_report(model, b_read, gfs, achieved, inf, A, sizes, traffic) -> dict:
     return rep
 
 
+SWEEP_SIGMAS = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536, 131072,
+                262144, 524288, 1048576, 2_000_000]
+
+
+def sigma_sweep(args):
+    """SELL-32-sigma on the power-law n = 2,000,000 matrix for sigma = 1 ..
+    n: beta, time and GF/s per sigma (the analog of the paper's sigma study of
+    kkt_power, Sect. 5.3). Under a counter run (--pmc-pass) each sigma runs
+    exactly 3 products so the dispatches can be attributed."""
+    import torch
+    import synth
+    from paper_1307_6209_amd import sellcs
+    A = synth.workload("powerlaw_2m")
+    r, c, v = to_dev(A)
+    x = torch.from_numpy(synth.uniform(A.ncols, synth.SEED_X + 1)).cuda()
+    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    rows = []
+    for sg in SWEEP_SIGMAS:
+        h = sellcs.sell_build(r, c, v, A.ncols, 32, sg)
+        if args.pmc_pass:
+            for _ in range(3):
+                sellcs.sell_spmv(h, x, y)
+            torch.cuda.synchronize()
+            t = float("nan")
+        else:
+            t = time_calls(lambda: sellcs.sell_spmv(h, x, y), 100, 10)
+        inf = h.info
+        rows.append({"sigma": sg, "beta": inf["beta"], "padded": inf["padded"], "nchunks": inf["nchunks"],
+                     "nsplit": inf["nsplit"], "us": round(t * 1e6, 2), "gfs": round(2.0 * A.nnz / t * 1e-9, 2)})
+        h.close()
+    if args.pmc_pass:
+        sellcs.sell_probe_bandwidth(1, 1 << 30, 1)
+        torch.cuda.synchronize()
+    print(json.dumps({"sigma_sweep": "powerlaw_2m", "C": 32, "n": A.nrows, "nnz": A.nnz, "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +240,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a few products and one copy probe")
+    ap.add_argument("--sigma-sweep", action="store_true", help="SELL-32-sigma sweep on the power-law matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the SELL-C-sigma product here is a single-device kernel "
@@ -215,6 +252,9 @@ def main():
     from paper_1307_6209_amd import model, sellcs
 
     torch.cuda.set_device(0)
+    if args.sigma_sweep:
+        sigma_sweep(args)
+        return
     A = synth.workload(HEADLINE["workload"])
     x_np = synth.uniform(A.ncols, synth.SEED_X + 2)
     r, c, v = to_dev(A)
