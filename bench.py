@@ -106,15 +106,16 @@ def run_forms(args) -> dict:
     # block form on the power-law n = 1,000,000 matrix
     A = synth.workload("powerlaw_1m")
     r, c, v = to_dev(A)
-    h = sellcs.sell_build(r, c, v, A.ncols, 32, 1024)
     spmmv = {}
-    for k in (1, 4, 8, 16, 32):
-        X = torch.from_numpy(synth.block_vector(A.ncols, k)).cuda()
-        Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
-        t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
-        spmmv["k%d" % k] = round(2.0 * A.nnz * k / t * 1e-9, 2)
+    for C, sg in ((32, 1024), (32, A.nrows)):
+        h = sellcs.sell_build(r, c, v, A.ncols, C, sg)
+        for k in (1, 4, 8, 16, 32):
+            X = torch.from_numpy(synth.block_vector(A.ncols, k)).cuda()
+            Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
+            t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
+            spmmv["C%d_sigma%d_k%d" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
+        h.close()
     out["spmmv_powerlaw_1m_gfs"] = spmmv
-    h.close()
     del r, c, v
     # 64 uneven power-law matrices in one persistent launch
     mats = synth.batch_workload(64)
@@ -310,15 +311,16 @@ def main():
         "probes": probes,
         "kernel_source_hash": src_hash,
     }
-    # precision forms on the same matrix
+    # precision forms on the same matrix, at the headline C and at C = 64
     forms = {}
     for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
-        hf = sellcs.sell_build(r, c, v, A.ncols, HEADLINE["C"], HEADLINE["sigma"], val_dtype=vd, acc_dtype=ad)
-        xf = x.float()
-        yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
-        t = time_calls(lambda: sellcs.sell_spmv(hf, xf, yf), max(50, args.steps // 4), 10)
-        forms["%s_val_%s_acc" % (vd, ad)] = round(2.0 * A.nnz / t * 1e-9, 2)
-        hf.close()
+        for C in sorted({HEADLINE["C"], 64}):
+            hf = sellcs.sell_build(r, c, v, A.ncols, C, HEADLINE["sigma"], val_dtype=vd, acc_dtype=ad)
+            xf = x.float()
+            yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
+            t = time_calls(lambda: sellcs.sell_spmv(hf, xf, yf), max(50, args.steps // 4), 10)
+            forms["%s_val_%s_acc_C%d" % (vd, ad, C)] = round(2.0 * A.nnz / t * 1e-9, 2)
+            hf.close()
     line["forms_stencil27_160_gfs"] = forms
     # the paper's comparison on one device: CRS (one lane per row, and L lanes
     # per row with a cross-lane reduction) against SELL-C-sigma

@@ -148,7 +148,8 @@ sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma,
  * x: device, ncols elements of the handle's x dtype (F64 or F32).
  * y: device, nrows elements of the accumulation dtype; fully overwritten,
  *    never read. x must not overlap y.
- * Padding slots multiply x[0] by zero, so x must be finite.
+ * Slots whose stored value is zero (all padding, and explicit zeros) are
+ * skipped: they contribute nothing, also where x holds Inf or NaN.
  * Calls on one handle must not overlap in time (they share the handle's
  * partial-sum buffer for split chunks): order them on one stream or
  * synchronise between streams.

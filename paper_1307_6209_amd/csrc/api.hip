@@ -428,7 +428,10 @@ extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t
   if (k == 1) return sell_spmv(h, X, Y, stream);
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: C must be >= 8 for k > 1");
   if (h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k exceeds the kmax given at build");
-  const int kv = choose_kv(h, k, h->ktile);
+  int kv = choose_kv(h, k, h->ktile);
+  // the gathers of KV contiguous right-hand sides are vector accesses: keep
+  // them aligned (X rows are k doubles apart, k % kv == 0 by choose_kv)
+  while (kv > 1 && (reinterpret_cast<uintptr_t>(X) % (sizeof(double) * kv)) != 0) kv >>= 1;
   const int KT = (64 / h->g.rpw) * kv;
   const int64_t ntiles = (k + KT - 1) / KT;
   if (h->units && ntiles * KT > next_pow2(h->kmax))

@@ -155,11 +155,12 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
       ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
       ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
     }
+    // padding slots hold value 0: their lanes skip the gather
     X xg[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < VV; ++v) xg[u][v] = x[ci[u][v]];
+      for (int v = 0; v < VV; ++v) xg[u][v] = raw[u][v] != 0 ? x[ci[u][v]] : (X)0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -188,7 +189,7 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < VV; ++v) xg[u][v] = ok[u] ? x[ci[u][v]] : (X)0;
+      for (int v = 0; v < VV; ++v) xg[u][v] = (ok[u] && raw[u][v] != 0) ? x[ci[u][v]] : (X)0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) {
@@ -206,6 +207,17 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
   const int64_t p0 = chunk * C + h * RPW + rl0;
   if (t != 0) return;
   if (nseg == 1) {
+    if constexpr (VV > 1) {
+      if (!perm && p0 + VV <= nrows &&
+          (reinterpret_cast<uintptr_t>(y + p0) & (VV * sizeof(A) - 1)) == 0) {  // VV consecutive rows: one store
+        typedef A avt __attribute__((ext_vector_type(VV)));
+        avt o;
+#pragma unroll
+        for (int v = 0; v < VV; ++v) o[v] = acc[v];
+        __builtin_nontemporal_store(o, reinterpret_cast<avt *>(y + p0));
+        return;
+      }
+    }
 #pragma unroll
     for (int v = 0; v < VV; ++v) {
       const int64_t p = p0 + v;
@@ -235,7 +247,15 @@ __device__ __forceinline__ void combine_split(const SplitDesc d, const int32_t *
   if (p >= nrows) return;
   const A *part = static_cast<const A *>(partial) + d.poff + lane;
   A sum = 0;
-  for (int q = 0; q < d.nseg; ++q) sum += part[(int64_t)q * RPW];
+  int q = 0;
+  for (; q + 8 <= d.nseg; q += 8) {  // eight loads in flight, added in order
+    A t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = part[(int64_t)(q + e) * RPW];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sum += t[e];
+  }
+  for (; q < d.nseg; ++q) sum += part[(int64_t)q * RPW];
   const int64_t row = perm ? (int64_t)perm[p] : p;
   static_cast<A *>(yv)[row] = sum;
 }
@@ -325,7 +345,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   constexpr int G = 64 / RPW;
   constexpr int WPC = C > 64 ? C / 64 : 1;
   constexpr int KT = G * KV;
-  constexpr int U = 2;
+  constexpr int U = KV >= 4 ? 2 : 8 / KV;  // chunk columns in flight: more when each lane gathers little
   using VecT = typename DVec<KV>::type;
 
   const int lane = threadIdx.x & 63;
@@ -376,9 +396,11 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
       vv[u] = ld_val(vp + (int64_t)(j + u) * C);
     }
     if (active) {
+      // padding slots hold value 0: their lanes skip the gather
       VecT xg[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) xg[u] = *reinterpret_cast<const VecT *>(X + (int64_t)ci[u] * k + v0);
+      for (int u = 0; u < U; ++u)
+        xg[u] = vv[u] != 0.0 ? *reinterpret_cast<const VecT *>(X + (int64_t)ci[u] * k + v0) : VecT{};
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -388,7 +410,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   for (; j < je; ++j) {
     const int32_t c = ld_col(cp + (int64_t)j * C);
     const double vj = ld_val(vp + (int64_t)j * C);
-    if (active) {
+    if (active && vj != 0.0) {
       const VecT xg = *reinterpret_cast<const VecT *>(X + (int64_t)c * k + v0);
 #pragma unroll
       for (int v = 0; v < KV; ++v) acc[v] = __builtin_fma(vj, vget<KV>(xg, v), acc[v]);

@@ -139,11 +139,47 @@ def _torch_dtype(code: int):
     return {0: torch.float64, 1: torch.float32}[code]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory for a handle from torch's caching allocator: every block
+    the library asks for is a uint8 tensor kept alive until the library frees
+    it (sell_destroy synchronises the device before freeing)."""
+
+    def __init__(self, fail_after: int | None = None):
+        self.live = {}
+        self.calls = 0
+        self.frees = 0
+        self.fail_after = fail_after  # return NULL from this allocation on (tests)
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._free = FREE_FN(self._on_free)
+        self.struct = SellAllocator(ctypes.cast(self._alloc, c_p), ctypes.cast(self._free, c_p), None)
+
+    def _on_alloc(self, nbytes, ctx):
+        import torch
+        self.calls += 1
+        if self.fail_after is not None and self.calls > self.fail_after:
+            return None
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _on_free(self, ptr, ctx):
+        self.frees += 1
+        self.live.pop(ptr, None)
+
+
 class SellMatrix:
     """A device-resident SELL-C-sigma matrix (wraps a sell_handle)."""
 
-    def __init__(self, handle: ctypes.c_void_p):
+    def __init__(self, handle: ctypes.c_void_p, allocator: TorchAllocator | None = None):
         self._h = handle
+        self.allocator = allocator  # keeps the callbacks and the blocks alive
         self.info = sell_info(self)
 
     @property
@@ -176,8 +212,11 @@ class SellMatrix:
 
 def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
                unroll: int = 0, vec: int = 0, seg_cols: int = 0, ktile: int = 0, kmax: int = 0,
-               permute_columns: bool = False, stream=None) -> SellMatrix:
-    """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64)."""
+               permute_columns: bool = False, allocator: TorchAllocator | None = None,
+               stream=None) -> SellMatrix:
+    """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64).
+    allocator: a TorchAllocator to take the handle's device memory from
+    torch's caching allocator (default: the library's hipMalloc)."""
     import torch
     nrows = rpt.numel() - 1
     nnz = col.numel()
@@ -186,10 +225,10 @@ def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "
     if acc_dtype is None:
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
     o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax,
-                      1 if permute_columns else 0, None)
+                      1 if permute_columns else 0, ctypes.pointer(allocator.struct) if allocator else None)
     h = c_p()
     _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
-    return SellMatrix(h)
+    return SellMatrix(h, allocator)
 
 
 def sell_spmv(h: SellMatrix, x, y, stream=None):

@@ -83,3 +83,21 @@ def test_host_side_argument_errors(L):
     assert L.sell_autotune(None, 1, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_destroy(None) == sellcs.SELL_OK
     assert L.sell_batch_destroy(None) == sellcs.SELL_OK
+
+
+def test_allocator_failure_is_reported_before_any_device_work(L):
+    """An allocator callback that returns NULL yields SELL_ERR_OOM; the
+    library asks it before launching anything, so this runs without a GPU."""
+    from paper_1307_6209_amd import sellcs
+    calls = []
+    alloc = sellcs.ALLOC_FN(lambda n, ctx: calls.append(n) or None)
+    free = sellcs.FREE_FN(lambda p, ctx: None)
+    al = sellcs.SellAllocator(ctypes.cast(alloc, ctypes.c_void_p), ctypes.cast(free, ctypes.c_void_p), None)
+    o = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, alloc=ctypes.pointer(al))
+    A = sellcs.SellCrs(10, 10, 0, ctypes.c_void_p(8), None, None)
+    h = ctypes.c_void_p()
+    assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(o), None, ctypes.byref(h)) == sellcs.SELL_ERR_OOM
+    assert calls and not h.value
+    half = sellcs.SellAllocator(ctypes.cast(alloc, ctypes.c_void_p), None, None)
+    o2 = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, alloc=ctypes.pointer(half))
+    assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(o2), None, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG

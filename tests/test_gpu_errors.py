@@ -53,3 +53,32 @@ def test_unsupported_and_invalid():
     with pytest.raises(TypeError):
         sellcs.sell_spmv(h, torch.zeros(A.ncols, dtype=torch.float64, device="cuda"),
                          torch.zeros(A.nrows, dtype=torch.float32, device="cuda"))
+
+
+@pytest.mark.parametrize("fail_after", [0, 1, 2, 3, 4, 5, 6, 7])
+def test_allocation_failure_midway_frees_everything(fail_after):
+    """The n-th device allocation fails: sell_build returns SELL_ERR_OOM and
+    every block it had obtained is given back to the allocator."""
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(20_000, seed=12)
+    rpt, col, val = dev_crs(A)
+    al = sellcs.TorchAllocator(fail_after=fail_after)
+    with pytest.raises(sellcs.SellError) as ei:
+        sellcs.sell_build(rpt, col, val, A.ncols, 32, 1, seg_cols=64, allocator=al)
+    assert ei.value.status == sellcs.SELL_ERR_OOM
+    assert not al.live and al.frees == min(fail_after, al.calls)
+
+
+def test_torch_allocator_build_and_destroy():
+    from paper_1307_6209_amd import sellcs
+    import torch
+    A = synth.powerlaw(20_000, seed=13)
+    rpt, col, val = dev_crs(A)
+    al = sellcs.TorchAllocator()
+    h = sellcs.sell_build(rpt, col, val, A.ncols, 32, 256, seg_cols=64, allocator=al)
+    assert al.live and h.info["device_bytes"] > 0
+    x = synth.uniform(A.ncols, 14, 1)
+    from gpu_util import spmv_gpu, check_fp64
+    check_fp64(A, spmv_gpu(h, x), x)
+    h.close()
+    assert not al.live and al.frees == al.calls

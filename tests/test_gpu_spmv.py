@@ -91,3 +91,19 @@ def test_laplacian_row_sums_exact():
         want[:, 0] += 1
         want[:, -1] += 1
         assert np.array_equal(g, want)
+
+
+@pytest.mark.parametrize("vec", [1, 2, 4])
+def test_misaligned_y_and_zero_entries(vec):
+    """y one element off a vector boundary (row stores fall back to scalar),
+    and explicit zero values among the stored entries."""
+    import torch
+    from paper_1307_6209_amd import sellcs
+    A = synth.stencil27(12)
+    A.val[::7] = 0.0
+    x = synth.uniform(A.ncols, 15, 1)
+    h = build(A, 32, 1, vec=vec)
+    yb = torch.full((A.nrows + 1,), float("nan"), dtype=torch.float64, device="cuda")
+    sellcs.sell_spmv(h, torch.from_numpy(x).cuda(), yb[1:])
+    torch.cuda.synchronize()
+    check_fp64(A, yb[1:].cpu().numpy(), x)
