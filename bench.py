@@ -117,25 +117,25 @@ def run_forms(args) -> dict:
         h.close()
     out["spmmv_powerlaw_1m_gfs"] = spmmv
     del r, c, v
-    # 64 uneven power-law matrices in one persistent launch
+    # 64 uneven power-law matrices in one persistent launch (sigma 1024, and
+    # sigma = n_b, the fastest on these matrices in the sigma sweep)
     mats = synth.batch_workload(64)
-    hs = []
-    for i, B in enumerate(mats):
-        rr, cc, vv = to_dev(B)
-        hs.append(sellcs.sell_build(rr, cc, vv, B.ncols, 32, 1024))
-    b = sellcs.sell_batch_create(hs)
+    devs = [to_dev(B) for B in mats]
     xs = [torch.from_numpy(synth.uniform(B.ncols, 5 + i)).cuda() for i, B in enumerate(mats)]
     ys = [torch.empty(B.nrows, dtype=torch.float64, device="cuda") for B in mats]
     nnz = sum(B.nnz for B in mats)
-    t = time_calls(lambda: sellcs.sell_batch_spmv(b, xs, ys), max(10, args.steps // 10), 3)
-    out["batch64_gfs"] = round(2.0 * nnz / t * 1e-9, 2)
-    out["batch64_us"] = round(t * 1e6, 2)
-    t_seq = time_calls(lambda: [sellcs.sell_spmv(hh, xx, yy) for hh, xx, yy in zip(hs, xs, ys)],
-                       max(5, args.steps // 50), 2)
-    out["batch64_separate_launches_us"] = round(t_seq * 1e6, 2)
-    b.close()
-    for hh in hs:
-        hh.close()
+    for tag, sig in (("sigma1024", lambda B: 1024), ("sigma_n", lambda B: B.nrows)):
+        hs = [sellcs.sell_build(rr, cc, vv, B.ncols, 32, sig(B)) for (rr, cc, vv), B in zip(devs, mats)]
+        b = sellcs.sell_batch_create(hs)
+        t = time_calls(lambda: sellcs.sell_batch_spmv(b, xs, ys), max(10, args.steps // 10), 3)
+        t_seq = time_calls(lambda: [sellcs.sell_spmv(hh, xx, yy) for hh, xx, yy in zip(hs, xs, ys)],
+                           max(5, args.steps // 50), 2)
+        out["batch64_%s" % tag] = {"gfs": round(2.0 * nnz / t * 1e-9, 2), "us": round(t * 1e6, 2),
+                                   "separate_launches_us": round(t_seq * 1e6, 2)}
+        b.close()
+        for hh in hs:
+            hh.close()
+    del devs
     # power-law n = 2,000,000: plain and globally sorted
     A = synth.workload("powerlaw_2m")
     r, c, v = to_dev(A)
@@ -331,6 +331,10 @@ def main():
         crs["crs_L%d" % L] = round(2.0 * A.nnz / t * 1e-9, 2)
     crs["sell_%d_%d" % (HEADLINE["C"], HEADLINE["sigma"])] = round(gfs, 2)
     line["crs_vs_sell_stencil27_160_gfs"] = crs
+    # SELL-32-1 against the autotuned SELL-C-sigma on the same matrix
+    tuned = sellcs.sell_autotune(r, c, v, A.ncols, k=1, C=(32, 64), sigma=(1, 1024, 131072), unroll=(4, 8), reps=20)
+    line["autotuned_stencil27_160"] = {key: (round(val, 3) if isinstance(val, float) else val)
+                                       for key, val in tuned.items()}
     h.close()
     del r, c, v
     if not args.no_forms:

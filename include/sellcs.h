@@ -236,6 +236,11 @@ typedef struct {
   const int32_t *ktile;   int32_t nktile;   /* used when k > 1 */
   sell_dtype val_dtype, acc_dtype;
   int32_t reps;           /* timed repetitions per candidate (0: 20) */
+  int32_t model_guided;   /* 0: time every (C, sigma). K > 0: rank all (C, sigma) by
+                             the bytes the code-balance model (Sect. 4, ideal alpha)
+                             assigns one product, from a layout-only build (row
+                             order, chunk widths; no values), and time only the K
+                             best */
 } sell_tune_space;
 
 typedef struct {
@@ -247,6 +252,7 @@ typedef struct {
   double us_per_call;
   double beta;
   int32_t candidates;   /* configurations measured */
+  int32_t predicted;    /* configurations ranked by the model (model_guided > 0) */
 } sell_tuned;
 
 /*

@@ -173,8 +173,13 @@ int32_t auto_seg_cols(int64_t total_steps, int T, int cus) {
 // ===========================================================================
 // Construction
 // ===========================================================================
-extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, const sell_build_opts *opts,
-                                  void *stream, sell_handle *out) {
+namespace {
+
+// The construction; with layout_only the handle stops after the row order,
+// chunk widths and offsets (no values, no column indices, no work plan) --
+// enough for beta and the model's byte count.
+sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_build_opts *opts, void *stream,
+                       sell_handle *out, bool layout_only) {
   if (!A || !out) return fail(SELL_ERR_INVALID_ARG, "sell_build: null argument");
   *out = nullptr;
   if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0) return fail(SELL_ERR_INVALID_ARG, "sell_build: negative size");
@@ -301,6 +306,14 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
     h->zeta = (double)(std::sqrt((double)var) / (double)mean);
   }
 
+  if (layout_only) {
+    SELL_HIP(hipStreamSynchronize(s));
+    h->nunits = h->nitems = nc * h->g.wpc;
+    guard.armed = false;
+    *out = h.release();
+    return SELL_OK;
+  }
+
   // padded column-major arrays
   if (h->padded > 0) {
     h->col = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * (size_t)h->padded));
@@ -361,6 +374,13 @@ extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, c
   guard.armed = false;
   *out = h.release();
   return SELL_OK;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma, const sell_build_opts *opts,
+                                  void *stream, sell_handle *out) {
+  return build_impl(A, C, sigma, opts, stream, out, false);
 }
 
 // ===========================================================================
@@ -790,11 +810,44 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
     }
   } ev{e0, e1};
 
+  // Model-guided search: rank every (C, sigma) by the bytes the code-balance
+  // model assigns one product (padded matrix, x once, y, permutation, chunk
+  // metadata -- Sect. 4 with the ideal alpha), from a layout-only build, and
+  // time only the best space.model_guided of them.
+  std::vector<std::pair<int, int>> order;
+  int predicted = 0;
+  if (sp.model_guided > 0) {
+    std::vector<std::pair<double, std::pair<int, int>>> ranked;
+    const double sv = (double)dtype_size(o.val_dtype), sx = (double)xs, sy = (double)ys;
+    for (int ic = 0; ic < nC; ++ic)
+      for (int is = 0; is < nS; ++is) {
+        sell_handle h = nullptr;
+        sell_status st = build_impl(A, Cs[ic], Ss[is], &o, stream, &h, true);
+        if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
+        if (st != SELL_OK) return st;
+        const double kk = (double)k;
+        double bytes = (sv + 4.0) * (double)h->padded + sx * kk * (double)A->ncols + sy * kk * (double)A->nrows +
+                       (h->perm ? 4.0 * (double)A->nrows : 0.0) + 12.0 * (double)h->nchunks;
+        ranked.push_back({bytes, {ic, is}});
+        ++predicted;
+        sell_destroy(h);
+      }
+    std::stable_sort(ranked.begin(), ranked.end(),
+                     [](const std::pair<double, std::pair<int, int>> &a, const std::pair<double, std::pair<int, int>> &b) {
+                       return a.first < b.first;
+                     });
+    for (size_t q = 0; q < ranked.size() && (int)q < sp.model_guided; ++q) order.push_back(ranked[q].second);
+  } else {
+    for (int ic = 0; ic < nC; ++ic)
+      for (int is = 0; is < nS; ++is) order.push_back({ic, is});
+  }
+
   sell_tuned r{};
   r.gflops = -1.0;
   int cands = 0;
-  for (int ic = 0; ic < nC; ++ic) {
-    for (int is = 0; is < nS; ++is) {
+  for (const auto &cand : order) {
+    {
+      const int ic = cand.first, is = cand.second;
       sell_handle h = nullptr;
       sell_status st = sell_build(A, Cs[ic], Ss[is], &o, stream, &h);
       if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
@@ -835,6 +888,7 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
     }
   }
   r.candidates = cands;
+  r.predicted = predicted;
   if (cands == 0) return fail(SELL_ERR_UNSUPPORTED, "sell_autotune: no configuration could be measured");
   *best = r;
   return SELL_OK;

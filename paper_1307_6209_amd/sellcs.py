@@ -56,12 +56,13 @@ class SellInfo(ctypes.Structure):
 class SellTuneSpace(ctypes.Structure):
     _fields_ = [("C", ctypes.POINTER(c_i32)), ("nC", c_i32), ("sigma", ctypes.POINTER(c_i64)), ("nsigma", c_i32),
                 ("unroll", ctypes.POINTER(c_i32)), ("nunroll", c_i32), ("ktile", ctypes.POINTER(c_i32)),
-                ("nktile", c_i32), ("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("reps", c_i32)]
+                ("nktile", c_i32), ("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("reps", c_i32),
+                ("model_guided", c_i32)]
 
 
 class SellTuned(ctypes.Structure):
     _fields_ = [("C", c_i32), ("sigma", c_i64), ("unroll", c_i32), ("ktile", c_i32), ("gflops", c_d),
-                ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32)]
+                ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32), ("predicted", c_i32)]
 
 
 # Every entry point the header declares: name -> (restype, argtypes).
@@ -345,8 +346,10 @@ def sell_batch_destroy(b: SellBatch):
 
 
 def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=(), ktile=(),
-                  val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0, stream=None) -> dict:
-    """Time every configuration of the search space; return the fastest."""
+                  val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0, model_guided: int = 0,
+                  stream=None) -> dict:
+    """Time the configurations of the search space (all of them, or the
+    model_guided best by the code-balance model); return the fastest."""
     import torch
     nrows = rpt.numel() - 1
     nnz = col.numel()
@@ -357,7 +360,7 @@ def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=
     arrs = [(c_i32 * len(C))(*C), (c_i64 * len(sigma))(*sigma), (c_i32 * len(unroll))(*unroll),
             (c_i32 * len(ktile))(*ktile)]
     sp = SellTuneSpace(arrs[0], len(C), arrs[1], len(sigma), arrs[2], len(unroll), arrs[3], len(ktile),
-                       DTYPES[val_dtype], DTYPES[acc_dtype], reps)
+                       DTYPES[val_dtype], DTYPES[acc_dtype], reps, model_guided)
     r = SellTuned()
     _check(lib().sell_autotune(ctypes.byref(A), k, ctypes.byref(sp), _stream(stream), ctypes.byref(r)), "sell_autotune")
     return {name: getattr(r, name) for name, _ in SellTuned._fields_}

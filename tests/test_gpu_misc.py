@@ -33,3 +33,17 @@ def test_autotune_block():
     r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=8, C=(16, 32), sigma=(1, 256), unroll=(8,), ktile=(0, 4, 8),
                              reps=3)
     assert r["candidates"] == 12 and r["ktile"] in (0, 4, 8)
+
+
+def test_autotune_model_guided():
+    """Model-guided search ranks all (C, sigma) by the model's bytes from a
+    layout-only build and times only the best few; on the power-law matrix
+    the global sort has the fewest bytes."""
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(200_000, seed=73)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(16, 32, 64), sigma=(1, 64, 4096, 200_000),
+                             unroll=(8,), reps=5, model_guided=2)
+    say("model guided", r)
+    assert r["predicted"] == 12 and r["candidates"] == 2
+    assert r["sigma"] == 200_000 and r["C"] in (16, 32, 64)
