@@ -148,8 +148,9 @@ sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma,
  * x: device, ncols elements of the handle's x dtype (F64 or F32).
  * y: device, nrows elements of the accumulation dtype; fully overwritten,
  *    never read. x must not overlap y.
- * Slots whose stored value is zero (all padding, and explicit zeros) are
- * skipped: they contribute nothing, also where x holds Inf or NaN.
+ * Padding slots (value 0, column 0) either multiply x[0] by zero or, on
+ * padding-heavy layouts (beta < 0.9), skip their gather -- as do explicit
+ * zero entries there -- so x must be finite.
  * Calls on one handle must not overlap in time (they share the handle's
  * partial-sum buffer for split chunks): order them on one stream or
  * synchronise between streams.

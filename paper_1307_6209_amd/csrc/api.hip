@@ -404,7 +404,6 @@ sell::SpmvArgs args_of(const sell_matrix *h, const void *x, void *y) {
   a.nsplit = h->units ? h->nsplit : 0;
   a.partial = h->partial;
   a.seg_cols = h->seg_cols;
-  a.swizzle = h->units ? 0 : 1;
   a.k = 1;
   a.kt = 1;
   return a;
@@ -417,7 +416,11 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   if ((h->nrows > 0 && !y) || (h->ncols > 0 && !x)) return fail(SELL_ERR_INVALID_ARG, "sell_spmv: null vector");
   if (h->nrows == 0) return SELL_OK;
   sell::SpmvArgs a = args_of(h, x, y);
-  hipError_t e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, a, static_cast<hipStream_t>(stream));
+  // padding-heavy layouts skip the gathers of their zero slots; near-dense
+  // chunks skip the per-slot test
+  const bool skip_zero = h->beta < 0.9;
+  hipError_t e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a,
+                                   static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail("sell_spmv launch", e);
   return SELL_OK;
 }

@@ -4,7 +4,7 @@
 namespace sell {
 
 #define SELL_DECL(lc)                                                                 \
-  hipError_t launch_spmv_##lc(int C, int U, int V, const SpmvArgs &a, hipStream_t s);      \
+  hipError_t launch_spmv_##lc(int C, int U, int V, bool sz, const SpmvArgs &a, hipStream_t s);      \
   hipError_t launch_batch_##lc(int C, int U, const BatchArgs &a, int gb, hipStream_t s); \
   int batch_waves_per_cu_##lc(int C, int U);
 SELL_DECL(f64_f64)
@@ -14,13 +14,13 @@ SELL_DECL(bf16_f32)
 SELL_DECL(bf16_f64)
 #undef SELL_DECL
 
-hipError_t launch_spmv(int combo, int C, int U, int V, const SpmvArgs &a, hipStream_t s) {
+hipError_t launch_spmv(int combo, int C, int U, int V, bool sz, const SpmvArgs &a, hipStream_t s) {
   switch (combo) {
-    case COMBO_F64_F64: return launch_spmv_f64_f64(C, U, V, a, s);
-    case COMBO_F32_F32: return launch_spmv_f32_f32(C, U, V, a, s);
-    case COMBO_F32_F64: return launch_spmv_f32_f64(C, U, V, a, s);
-    case COMBO_BF16_F32: return launch_spmv_bf16_f32(C, U, V, a, s);
-    case COMBO_BF16_F64: return launch_spmv_bf16_f64(C, U, V, a, s);
+    case COMBO_F64_F64: return launch_spmv_f64_f64(C, U, V, sz, a, s);
+    case COMBO_F32_F32: return launch_spmv_f32_f32(C, U, V, sz, a, s);
+    case COMBO_F32_F64: return launch_spmv_f32_f64(C, U, V, sz, a, s);
+    case COMBO_BF16_F32: return launch_spmv_bf16_f32(C, U, V, sz, a, s);
+    case COMBO_BF16_F64: return launch_spmv_bf16_f64(C, U, V, sz, a, s);
   }
   return hipErrorInvalidValue;
 }

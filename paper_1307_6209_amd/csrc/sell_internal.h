@@ -84,7 +84,6 @@ struct SpmvArgs {
   int64_t nsplit;
   void *partial;
   int32_t seg_cols;     // chunk columns per segment (multiple of kSegAlign)
-  int32_t swizzle;      // map consecutive work to one XCD
   // block form only
   int32_t k;            // right-hand sides
   int32_t kt;           // right-hand sides per pass (ktile)
@@ -133,7 +132,8 @@ enum DtypeCombo {
 // Kernel launchers (return hipError of the launch).
 // Each launcher enqueues the product kernel and, when rows are split, the
 // kernel that adds their segment sums.
-hipError_t launch_spmv(int combo, int C, int U, int V, const SpmvArgs &a, hipStream_t s);
+// skip_zero: slots holding value 0 skip their gather (for padding-heavy layouts).
+hipError_t launch_spmv(int combo, int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, int grid_blocks, hipStream_t s);
 int batch_waves_per_cu(int combo, int C, int U);

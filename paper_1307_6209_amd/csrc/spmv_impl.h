@@ -15,7 +15,10 @@
 // per-row scheme the paper discusses for GPUs, Sects. 3.4 and 5.2, done
 // inside one wavefront). val and col are read once, with non-temporal
 // loads, so that the x vector keeps the caches; x is gathered through
-// L2/MALL.
+// L2/MALL. Consecutive workgroups take consecutive chunks: all XCDs stream
+// neighbouring parts of the matrix at the same time (measured faster than
+// giving each XCD a contiguous range of its own, which keeps x in one L2
+// but spreads the streams over eight distant regions).
 //
 // Long chunks. A chunk wider than seg_cols columns is cut into
 // segments that run on different waves; each segment stores its row sums in
@@ -91,15 +94,6 @@ __device__ __forceinline__ double fmac(float v, float x, double acc) {
 }
 __device__ __forceinline__ float fmac(float v, float x, float acc) { return __builtin_fmaf(v, x, acc); }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).
-// Renumber them so that each XCD receives one contiguous range of the work:
-// rows that are close share x entries, and then share one L2.
-__device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t nb) {
-  const int64_t q = nb >> 3, rem = nb & 7;
-  const int64_t x = b & 7, i = b >> 3;
-  return x * q + (x < rem ? x : rem) + i;
-}
-
 constexpr int kWavesPerBlock = 4;
 
 // One work unit: rows [h*rpw, (h+1)*rpw) of chunk `chunk`, chunk columns
@@ -108,7 +102,9 @@ constexpr int kWavesPerBlock = 4;
 // Lane l holds the VV consecutive slots VV*l .. VV*l+VV-1 of every wave step
 // (64*VV consecutive slots = T chunk columns of RPW rows): rows
 // rl0 .. rl0+VV-1 with rl0 = (VV*l) % RPW, column offset t = (VV*l) / RPW.
-template <int COMBO, int C, int U, int VV>
+// With ZS, slots holding value 0 (padding) skip the gather; that pays on
+// padding-heavy layouts and costs a compare per slot on dense ones.
+template <int COMBO, int C, int U, int VV, bool ZS>
 __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const int32_t *__restrict__ col,
                                           const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
                                           const int32_t *__restrict__ perm, const void *__restrict__ xv,
@@ -155,12 +151,11 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
       ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
       ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
     }
-    // padding slots hold value 0: their lanes skip the gather
     X xg[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < VV; ++v) xg[u][v] = raw[u][v] != 0 ? x[ci[u][v]] : (X)0;
+      for (int v = 0; v < VV; ++v) xg[u][v] = (!ZS || raw[u][v] != 0) ? x[ci[u][v]] : (X)0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -189,7 +184,7 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < VV; ++v) xg[u][v] = (ok[u] && raw[u][v] != 0) ? x[ci[u][v]] : (X)0;
+      for (int v = 0; v < VV; ++v) xg[u][v] = (ok[u] && (!ZS || raw[u][v] != 0)) ? x[ci[u][v]] : (X)0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) {
@@ -267,11 +262,10 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_combine(SpmvArgs a) {
   combine_split<COMBO, C>(a.splits[w], a.perm, a.partial, a.y, a.nrows, threadIdx.x & 63);
 }
 
-template <int COMBO, int C, int U, int VV>
+template <int COMBO, int C, int U, int VV, bool ZS>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t b = a.swizzle ? xcd_swizzle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-  const int64_t w = b * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (w >= a.nwork) return;
   int32_t item, seg = 0, nseg = 1;
   int64_t poff = 0;
@@ -284,8 +278,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
   } else {
     item = (int32_t)w;
   }
-  spmv_unit<COMBO, C, U, VV>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff, a.partial,
-                             a.seg_cols, lane);
+  spmv_unit<COMBO, C, U, VV, ZS>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff,
+                                 a.partial, a.seg_cols, lane);
 }
 
 // Persistent batched form: wave w runs units [slice[w], slice[w+1]) of the
@@ -300,8 +294,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
     const BUnit u = a.units[q];
     const BatchMat m = a.mats[u.mat];
     const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
-    spmv_unit<COMBO, C, U, 1>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg, poff,
-                              a.partial, a.seg_cols, lane);
+    spmv_unit<COMBO, C, U, 1, true>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg,
+                                    poff, a.partial, a.seg_cols, lane);
   }
 }
 
@@ -349,8 +343,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   using VecT = typename DVec<KV>::type;
 
   const int lane = threadIdx.x & 63;
-  const int64_t b = a.swizzle ? xcd_swizzle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-  const int64_t w = b * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (w >= a.nwork) return;
   int32_t item, seg = 0, nseg = 1;
   int64_t poff = 0;
@@ -480,13 +473,13 @@ namespace dev {
   X(1, 4) X(1, 8) X(2, 4) X(2, 8) X(4, 4) X(4, 8) X(8, 4) X(8, 8) X(16, 4) X(16, 8) X(32, 4) X(32, 8) X(64, 4) \
       X(64, 8) X(128, 4) X(128, 8)
 
-template <int COMBO>
-hipError_t launch_spmv_t(int C, int U, int VV, const SpmvArgs &a, hipStream_t s) {
+template <int COMBO, bool ZS>
+hipError_t launch_spmv_zs(int C, int U, int VV, const SpmvArgs &a, hipStream_t s) {
   if (a.nwork <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((a.nwork + kWavesPerBlock - 1) / kWavesPerBlock);
 #define SELL_L(CC, UU, VVV)                                                                                  \
   if (C == CC && U == UU && VV == VVV) {                                                                    \
-    hipLaunchKernelGGL((k_spmv<COMBO, CC, UU, VVV>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);         \
+    hipLaunchKernelGGL((k_spmv<COMBO, CC, UU, VVV, ZS>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);     \
     hipError_t e_ = hipGetLastError();                                                                       \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                        \
     const unsigned nbc = (unsigned)((a.nsplit + kWavesPerBlock - 1) / kWavesPerBlock);                        \
@@ -496,6 +489,11 @@ hipError_t launch_spmv_t(int C, int U, int VV, const SpmvArgs &a, hipStream_t s)
   SELL_FOR_EACH_CUV(SELL_L)
 #undef SELL_L
   return hipErrorInvalidValue;
+}
+
+template <int COMBO>
+hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a, hipStream_t s) {
+  return skip_zero ? launch_spmv_zs<COMBO, true>(C, U, VV, a, s) : launch_spmv_zs<COMBO, false>(C, U, VV, a, s);
 }
 
 template <int COMBO>
