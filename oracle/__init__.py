@@ -41,7 +41,13 @@ def _L():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        _lib = configure(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def configure(lib):
+    """Declare the C signatures on a loaded oracle library."""
+    if True:
         i64, i32, p, d = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double
         lib.or_crs_validate.argtypes = [i64, i64, i64, p, p]
         lib.or_crs_validate.restype = ctypes.c_int
@@ -62,8 +68,7 @@ def _L():
         lib.or_round_f32.argtypes = [i64, p, p]
         lib.or_round_bf16.argtypes = [i64, p, p]
         lib.or_bf16_to_f64.argtypes = [i64, p, p]
-        _lib = lib
-    return _lib
+    return lib
 
 
 def _p(a: np.ndarray):

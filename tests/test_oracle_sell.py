@@ -201,3 +201,19 @@ def test_symmetric_permutation_identity(sigma):
     assert np.array_equal(S["cs"], D["cs"]) and np.array_equal(S["perm"], D["perm"])
     assert np.array_equal(oracle.sell_spmv(dict(S, perm=np.arange(A.nrows, dtype=np.int32)), A.nrows, x[perm]),
                           oracle.crs_spmv(A, x)[perm])
+
+
+@pytest.mark.parametrize("C", [2, 4, 8, 32])
+def test_staircase_beta(C):
+    """Row i holds (i mod C) + 1 entries: with sigma = 1 every chunk's
+    longest row is its last, cl = C, and beta = (C + 1) / (2 C); with
+    sigma = C the rows of a chunk are reversed and beta is unchanged."""
+    nch = 50
+    n = nch * C
+    lens = np.arange(n, dtype=np.int64) % C + 1
+    A = synth.CRS(n, C, np.concatenate([[0], np.cumsum(lens)]), np.concatenate([np.arange(l, dtype=np.int32) for l in lens]),
+                  np.ones(int(lens.sum())))
+    for sigma in (1, C):
+        S = oracle.sell_build(A, C, sigma)
+        assert np.all(S["cl"] == C)
+        assert S["padded"] * (C + 1) == A.nnz * 2 * C
