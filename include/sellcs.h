@@ -235,6 +235,10 @@ typedef struct {
   const int64_t *sigma;   int32_t nsigma;   /* sorting scopes */
   const int32_t *unroll;  int32_t nunroll;
   const int32_t *ktile;   int32_t nktile;   /* used when k > 1 */
+  const int32_t *vec;     int32_t nvec;     /* slots per lane (0 = default); with C this sets
+                                               the lanes per row, 64 * vec / C */
+  const int32_t *seg_cols; int32_t nseg_cols; /* split width of long chunks (0 = automatic):
+                                               how many waves share a long row */
   sell_dtype val_dtype, acc_dtype;
   int32_t reps;           /* timed repetitions per candidate (0: 20) */
   int32_t model_guided;   /* 0: time every (C, sigma). K > 0: rank all (C, sigma) by
@@ -249,6 +253,8 @@ typedef struct {
   int64_t sigma;
   int32_t unroll;
   int32_t ktile;
+  int32_t vec;
+  int32_t seg_cols;
   double gflops;        /* useful 2 * nnz * k flops per second / 1e9 */
   double us_per_call;
   double beta;

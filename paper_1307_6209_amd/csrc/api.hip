@@ -789,6 +789,11 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   const int32_t *Ks = sp.nktile > 0 ? sp.ktile : defK;
   int nK = sp.nktile > 0 ? sp.nktile : 1;
   const int reps = sp.reps > 0 ? sp.reps : 20;
+  const int32_t defV[] = {0}, defSeg[] = {0};
+  const int32_t *Vs = sp.nvec > 0 ? sp.vec : defV;
+  int nV = sp.nvec > 0 ? sp.nvec : 1;
+  const int32_t *Gs = sp.nseg_cols > 0 ? sp.seg_cols : defSeg;
+  int nG = sp.nseg_cols > 0 ? sp.nseg_cols : 1;
   sell_build_opts o{};
   o.val_dtype = sp.val_dtype;
   o.acc_dtype = sp.acc_dtype;
@@ -849,8 +854,11 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   r.gflops = -1.0;
   int cands = 0;
   for (const auto &cand : order) {
-    {
+    for (int iv = 0; iv < nV * nG; ++iv) {
       const int ic = cand.first, is = cand.second;
+      // slots per lane and split width are build parameters: one build each
+      o.vec = Vs[iv % nV];
+      o.seg_cols = Gs[iv / nV];
       sell_handle h = nullptr;
       sell_status st = sell_build(A, Cs[ic], Ss[is], &o, stream, &h);
       if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
@@ -879,6 +887,8 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
           if (gf > r.gflops) {
             r.C = Cs[ic];
             r.sigma = Ss[is];
+            r.vec = h->g.V;
+            r.seg_cols = h->seg_cols;
             r.unroll = Us[iu];
             r.ktile = h->ktile;
             r.gflops = gf;

@@ -47,3 +47,17 @@ def test_autotune_model_guided():
     say("model guided", r)
     assert r["predicted"] == 12 and r["candidates"] == 2
     assert r["sigma"] == 200_000 and r["C"] in (16, 32, 64)
+
+
+def test_autotune_lanes_per_row_and_split_width():
+    """vec (lanes per row = 64 vec / C) and the split width of long rows are
+    searched too; unsupported combinations are skipped."""
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(100_000, seed=74)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(32, 128), sigma=(100_000,), unroll=(8,), vec=(1, 2, 4),
+                             seg_cols=(64, 256), reps=5)
+    say("autotune vec/seg", r)
+    # C = 128 accepts vec 1 only: 3*2 builds for C = 32, 1*2 for C = 128
+    assert r["candidates"] == 8
+    assert r["vec"] in (1, 2, 4) and r["seg_cols"] in (64, 256)
