@@ -79,22 +79,76 @@ def time_calls(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) * 1e-3 / steps
 
 
-def cpu_baseline(A, x, budget_s: float = 10.0) -> dict:
-    """The oracle's CRS product on the host cores (OpenMP over rows)."""
+def cpu_baseline(A, x, budget_s: float = 10.0, C: int = 32, sigma: int = 1) -> dict:
+    """The oracle's CRS product on the host cores (OpenMP over rows), the
+    same product on one core, and the oracle's SELL-C-sigma build time."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     sched = oracle.schedule_for(A)
+
+    def per_call(nthreads, budget):
+        t0 = time.perf_counter()
+        oracle.crs_spmv(A, x, nthreads=nthreads, sched=sched)
+        t1 = time.perf_counter() - t0
+        reps = int(max(3, min(500, budget / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.crs_spmv(A, x, nthreads=nthreads, sched=sched)
+        return (time.perf_counter() - t0) / reps, reps
+
+    t, reps = per_call(threads, budget_s)
+    t_one, reps_one = per_call(1, budget_s / 2)
     t0 = time.perf_counter()
-    oracle.crs_spmv(A, x, nthreads=threads, sched=sched)
-    t1 = time.perf_counter() - t0
-    reps = int(max(3, min(500, budget_s / max(t1, 1e-6))))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        oracle.crs_spmv(A, x, nthreads=threads, sched=sched)
-    t = (time.perf_counter() - t0) / reps
+    oracle.sell_build(A, C, sigma)
+    t_build = time.perf_counter() - t0
     return {"value": round(2.0 * A.nnz / t * 1e-9, 3), "unit": "GF/s", "cores": threads, "kind": "oracle",
             "sample": "full %s matrix (%d nonzeros), CRS product in double, %d repetitions, OpenMP %s" % (
-                A.name, A.nnz, reps, "static" if sched == 0 else "guided,1")}
+                A.name, A.nnz, reps, "static" if sched == 0 else "guided,1"),
+            "one_core_value": round(2.0 * A.nnz / t_one * 1e-9, 3), "one_core_repetitions": reps_one,
+            "sell_build_ms": round(t_build * 1e3, 1), "sell_build_format": "SELL-%d-%d" % (C, sigma)}
+
+
+def graph_time(fn, launches: int, replays: int = 5) -> float:
+    """Seconds per call of fn from a captured graph of `launches` calls,
+    replayed back to back (launch overhead amortised)."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        fn()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(launches):
+                fn()
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / (replays * launches)
+
+
+def cold_time(fn, flush, reps: int = 21) -> float:
+    """Median seconds of single calls of fn, each timed by its own events
+    right after a read-modify-write of `flush` (1 GiB: evicts every L2 and
+    the 256 MB Infinity Cache)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        flush.add_(1.0)
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    return ts[len(ts) // 2] * 1e-3
 
 
 def run_forms(args) -> dict:
@@ -103,6 +157,20 @@ def run_forms(args) -> dict:
     import synth
     from paper_1307_6209_amd import sellcs
     out = {}
+    flush = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
+    # the small, cache-resident 5-point Laplacian 128^2 (SELL-32-1): per-call
+    # time from back-to-back launches and from a graph of 1000 launches
+    A = synth.workload("lap5_128")
+    r, c, v = to_dev(A)
+    h = sellcs.sell_build(r, c, v, A.ncols, 32, 1)
+    x = torch.from_numpy(synth.uniform(A.ncols, synth.SEED_X)).cuda()
+    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    t_eager = time_calls(lambda: sellcs.sell_spmv(h, x, y), 1000, 20)
+    t_graph = graph_time(lambda: sellcs.sell_spmv(h, x, y), 1000)
+    out["lap5_128"] = {"us_per_call_stream": round(t_eager * 1e6, 3), "us_per_call_graph": round(t_graph * 1e6, 3),
+                       "gfs_graph": round(2.0 * A.nnz / t_graph * 1e-9, 2)}
+    h.close()
+    del r, c, v
     # block form on the power-law n = 1,000,000 matrix
     A = synth.workload("powerlaw_1m")
     r, c, v = to_dev(A)
@@ -114,6 +182,9 @@ def run_forms(args) -> dict:
             Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
             t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
             spmmv["C%d_sigma%d_k%d" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
+            if sg == A.nrows and k in (1, 8, 32):
+                t = cold_time(lambda: sellcs.sell_spmmv(h, X, Y), flush)
+                spmmv["C%d_sigma%d_k%d_cold" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
         h.close()
     out["spmmv_powerlaw_1m_gfs"] = spmmv
     del r, c, v
@@ -130,8 +201,10 @@ def run_forms(args) -> dict:
         t = time_calls(lambda: sellcs.sell_batch_spmv(b, xs, ys), max(10, args.steps // 10), 3)
         t_seq = time_calls(lambda: [sellcs.sell_spmv(hh, xx, yy) for hh, xx, yy in zip(hs, xs, ys)],
                            max(5, args.steps // 50), 2)
+        t_cold = cold_time(lambda: sellcs.sell_batch_spmv(b, xs, ys), flush)
         out["batch64_%s" % tag] = {"gfs": round(2.0 * nnz / t * 1e-9, 2), "us": round(t * 1e6, 2),
-                                   "separate_launches_us": round(t_seq * 1e6, 2)}
+                                   "separate_launches_us": round(t_seq * 1e6, 2),
+                                   "cold_gfs": round(2.0 * nnz / t_cold * 1e-9, 2)}
         b.close()
         for hh in hs:
             hh.close()
@@ -145,7 +218,17 @@ def run_forms(args) -> dict:
     for C, s in ((32, 1), (32, 2**14), (32, A.nrows), (16, A.nrows)):
         h = sellcs.sell_build(r, c, v, A.ncols, C, s)
         t = time_calls(lambda: sellcs.sell_spmv(h, x, y), max(20, args.steps // 5), 5)
-        pl["C%d_sigma%d" % (C, s)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(h.info["beta"], 4)}
+        t_cold = cold_time(lambda: sellcs.sell_spmv(h, x, y), flush)
+        pl["C%d_sigma%d" % (C, s)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(h.info["beta"], 4),
+                                      "cold_gfs": round(2.0 * A.nnz / t_cold * 1e-9, 2)}
+        h.close()
+    # reduced-precision storage at the globally sorted layout
+    xf = x.float()
+    for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
+        h = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, val_dtype=vd, acc_dtype=ad)
+        yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
+        t = time_calls(lambda: sellcs.sell_spmv(h, xf, yf), max(20, args.steps // 5), 5)
+        pl["C32_sigma%d_%s_val_%s_acc" % (A.nrows, vd, ad)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2)}
         h.close()
     hs_ = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, permute_columns=True)
     xp = torch.empty_like(x)
@@ -340,7 +423,7 @@ def main():
     if not args.no_forms:
         line["forms"] = run_forms(args)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(A, x_np)
+        line["cpu_baseline"] = cpu_baseline(A, x_np, C=HEADLINE["C"], sigma=HEADLINE["sigma"])
     print(json.dumps(line))
 
 

@@ -154,6 +154,8 @@ sell_status sell_build(const sell_crs *A, int32_t C, int64_t sigma,
  * Calls on one handle must not overlap in time (they share the handle's
  * partial-sum buffer for split chunks): order them on one stream or
  * synchronise between streams.
+ * The call only enqueues kernels (no allocation, copy, memset or
+ * synchronisation), so it may be captured into a HIP graph.
  */
 sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream);
 

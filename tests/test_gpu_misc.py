@@ -61,3 +61,40 @@ def test_autotune_lanes_per_row_and_split_width():
     # C = 128 accepts vec 1 only: 3*2 builds for C = 32, 1*2 for C = 128
     assert r["candidates"] == 8
     assert r["vec"] in (1, 2, 4) and r["seg_cols"] in (64, 256)
+
+
+def test_spmv_in_captured_graph():
+    """sell_spmv launches can be captured in a graph (no allocation or
+    synchronisation inside); replays with eager work between them match
+    the eager result bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1307_6209_amd import sellcs
+    A = synth.lap5(128)
+    rpt, col, val = dev_crs(A)
+    h = sellcs.sell_build(rpt, col, val, A.ncols, 32, 1)
+    hs = sellcs.sell_build(rpt, col, val, A.ncols, 16, A.nrows, seg_cols=64)
+    x = torch.from_numpy(synth.uniform(A.ncols, 75, 1)).cuda()
+    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    y2 = torch.empty_like(y)
+    sellcs.sell_spmv(h, x, y)
+    sellcs.sell_spmv(hs, x, y2)
+    torch.cuda.synchronize()
+    want, want2 = y.cpu().numpy().copy(), y2.cpu().numpy().copy()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(5):
+                sellcs.sell_spmv(h, x, y)
+                sellcs.sell_spmv(hs, x, y2)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        y2.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), want) and np.array_equal(y2.cpu().numpy(), want2)
+        sellcs.sell_spmv(hs, x, y2)  # eager work between replays
+        torch.cuda.synchronize()
