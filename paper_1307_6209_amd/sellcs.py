@@ -90,13 +90,37 @@ SIGNATURES = {
 }
 
 
+def hip_runtimes() -> list:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if line.strip() else ""
+                if "libamdhip64.so" in os.path.basename(path):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return sorted(found)
+
+
 def lib():
-    """The loaded libsellcs.so (raises if it has not been built)."""
+    """The loaded libsellcs.so (raises if it has not been built).
+
+    torch is imported first: it loads the HIP runtime it ships with, and the
+    library then binds to that same runtime (same soname) instead of loading
+    a second one from the ROCm install. Two HIP runtimes in one process do
+    not share device state, and allocations through the second one fail."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libsellcs.so is not built (run: python -m paper_1307_6209_amd._build)")
+        import torch  # noqa: F401  (loads torch's HIP runtime before the library)
         L = ctypes.CDLL(LIB_PATH)
+        rts = hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError("two HIP runtimes are loaded (%s); import torch before loading libsellcs.so"
+                               % ", ".join(rts))
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
             fn.restype = res

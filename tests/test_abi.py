@@ -4,6 +4,7 @@ status codes. No kernel is launched here."""
 import ctypes
 import os
 import re
+import sys
 
 import pytest
 
@@ -101,3 +102,17 @@ def test_allocator_failure_is_reported_before_any_device_work(L):
     half = sellcs.SellAllocator(ctypes.cast(alloc, ctypes.c_void_p), None, None)
     o2 = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, alloc=ctypes.pointer(half))
     assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(o2), None, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Loading the library through the binding maps one HIP runtime (torch's):
+    a second runtime in the process does not share device state with torch,
+    and every allocation through it fails."""
+    import subprocess
+    code = ("from paper_1307_6209_amd import sellcs; sellcs.lib(); "
+            "import json; print(json.dumps(sellcs.hip_runtimes()))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    import json
+    rts = json.loads(out.stdout.strip().splitlines()[-1])
+    assert len(rts) == 1, rts
