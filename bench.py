@@ -188,7 +188,7 @@ def run_forms(args) -> dict:
         h.close()
     out["spmmv_powerlaw_1m_gfs"] = spmmv
     del r, c, v
-    # 64 uneven power-law matrices in one persistent launch (sigma 1024, and
+    # 64 uneven power-law matrices in one graph launch (sigma 1024, and
     # sigma = n_b, the fastest on these matrices in the sigma sweep)
     mats = synth.batch_workload(64)
     devs = [to_dev(B) for B in mats]

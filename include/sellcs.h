@@ -189,11 +189,12 @@ sell_status sell_export(sell_handle h, int32_t *perm, int32_t *cl, int64_t *cs,
 sell_status sell_destroy(sell_handle h);
 
 /*
- * sell_batch_create -- prepare one persistent launch that multiplies count
- * matrices with their own vectors. All handles must share C and dtypes;
- * they are borrowed and must outlive the batch. The work of all matrices
- * (chunk slices, long chunks split) is divided into equal-cost slices, one
- * per resident wavefront, and the launch is captured once in a hipGraph.
+ * sell_batch_create -- prepare one launch that multiplies count matrices
+ * with their own vectors. All handles must share C and dtypes; they are
+ * borrowed and must outlive the batch. The work units of all matrices
+ * (chunk row slices, long chunks split into segments, the segments first)
+ * are concatenated, one wavefront per unit, and the launch is captured once
+ * in a hipGraph.
  */
 sell_status sell_batch_create(const sell_handle *hs, int32_t count,
                               sell_batch *out);

@@ -1,6 +1,6 @@
 // Host side of the SELL-C-sigma library: argument checking, device memory,
 // the construction pipeline, work planning for long chunks, the batched
-// persistent launch with its hipGraph, the autotuner and the probes.
+// launch with its hipGraph, the autotuner and the probes.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -524,18 +524,16 @@ extern "C" sell_status sell_destroy(sell_handle h) {
 }
 
 // ===========================================================================
-// Batched persistent launch
+// Batched launch
 // ===========================================================================
 struct sell_batch_s {
   std::vector<sell_handle> hs;
   int combo = 0, C = 0, U = 8;
   Geom g{};
   int32_t seg_cols = 0;
-  int nwaves = 0, grid_blocks = 0;
   int64_t nunits = 0, nsplit = 0;
   sell::BatchMat *mats = nullptr;
   sell::BUnit *units = nullptr;
-  int32_t *slice = nullptr;
   sell::BSplitDesc *splits = nullptr;
   void *partial = nullptr;
   std::vector<sell::BatchMat> host_mats;
@@ -600,64 +598,41 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   DeviceInfo di = device_info();
   const int32_t S = auto_seg_cols(total, g.T, di.cus);
   B->seg_cols = S;
+  // split units of every matrix first (the longest work starts earliest),
+  // then the whole items; one wave per unit
   std::vector<sell::BUnit> units;
-  std::vector<int64_t> cost;  // per unit, in wave steps plus a fixed charge
   std::vector<sell::BSplitDesc> splits;
   int64_t off = 0;
-  const int64_t kFixed = 4;
   for (int32_t b = 0; b < count; ++b) {
     const ItemCols &s = st[b];
     for (size_t it = 0; it < s.cols.size(); ++it) {
-      int32_t w = s.cols[it];
-      if (w <= S) {
-        units.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
-        cost.push_back((w + g.T - 1) / g.T + kFixed);
-      } else {
-        int32_t nseg = (w + S - 1) / S;
-        int32_t sid = (int32_t)splits.size();
-        splits.push_back({b, (int32_t)it, nseg, 0, off});
-        off += (int64_t)nseg * g.rpw;
-        for (int32_t q = 0; q < nseg; ++q) {
-          units.push_back({b, (int32_t)it, q, nseg, sid, {0, 0, 0}});
-          cost.push_back((std::min<int64_t>(S, w - (int64_t)q * S) + g.T - 1) / g.T + kFixed);
-        }
-      }
+      const int32_t w = s.cols[it];
+      if (w <= S) continue;
+      const int32_t nseg = (w + S - 1) / S;
+      const int32_t sid = (int32_t)splits.size();
+      splits.push_back({b, (int32_t)it, nseg, 0, off});
+      off += (int64_t)nseg * g.rpw;
+      for (int32_t q = 0; q < nseg; ++q) units.push_back({b, (int32_t)it, q, nseg, sid, {0, 0, 0}});
     }
+  }
+  for (int32_t b = 0; b < count; ++b) {
+    const ItemCols &s = st[b];
+    for (size_t it = 0; it < s.cols.size(); ++it)
+      if (s.cols[it] <= S) units.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
   }
   B->nunits = (int64_t)units.size();
   B->nsplit = (int64_t)splits.size();
   if (B->nunits >= ((int64_t)1 << 31)) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_create: too many work units");
 
-  // one slice of equal cost per resident wave
-  const int wpcu = std::max(1, sell::batch_waves_per_cu(B->combo, B->C, B->U));
-  int64_t nwaves = (int64_t)di.cus * wpcu;
-  nwaves = std::max<int64_t>(4, std::min<int64_t>(nwaves, B->nunits));
-  nwaves = (nwaves + 3) / 4 * 4;
-  B->nwaves = (int)nwaves;
-  B->grid_blocks = (int)(nwaves / 4);
-  int64_t tot_cost = 0;
-  for (int64_t c : cost) tot_cost += c;
-  std::vector<int32_t> slice((size_t)nwaves + 1, (int32_t)B->nunits);
-  slice[0] = 0;
-  {
-    int64_t acc = 0;
-    int64_t w = 1;
-    for (int64_t u = 0; u < B->nunits && w < nwaves; ++u) {
-      acc += cost[(size_t)u];
-      while (w < nwaves && acc * nwaves >= w * tot_cost) slice[(size_t)w++] = (int32_t)(u + 1);
-    }
-  }
-
   B->mats = static_cast<sell::BatchMat *>(batch_alloc(B.get(), sizeof(sell::BatchMat) * (size_t)count));
-  B->units = static_cast<sell::BUnit *>(batch_alloc(B.get(), sizeof(sell::BUnit) * units.size()));
-  B->slice = static_cast<int32_t *>(batch_alloc(B.get(), sizeof(int32_t) * slice.size()));
+  B->units = static_cast<sell::BUnit *>(batch_alloc(B.get(), sizeof(sell::BUnit) * std::max<size_t>(1, units.size())));
   B->splits = static_cast<sell::BSplitDesc *>(
       batch_alloc(B.get(), sizeof(sell::BSplitDesc) * std::max<size_t>(1, splits.size())));
   B->partial = batch_alloc(B.get(), sizeof(double) * (size_t)std::max<int64_t>(1, off));
-  if (!B->mats || !B->units || !B->slice || !B->splits || !B->partial)
+  if (!B->mats || !B->units || !B->splits || !B->partial)
     return fail(SELL_ERR_OOM, "sell_batch_create: allocation failed");
-  SELL_HIP(hipMemcpy(B->units, units.data(), sizeof(sell::BUnit) * units.size(), hipMemcpyHostToDevice));
-  SELL_HIP(hipMemcpy(B->slice, slice.data(), sizeof(int32_t) * slice.size(), hipMemcpyHostToDevice));
+  if (!units.empty())
+    SELL_HIP(hipMemcpy(B->units, units.data(), sizeof(sell::BUnit) * units.size(), hipMemcpyHostToDevice));
   if (!splits.empty())
     SELL_HIP(hipMemcpy(B->splits, splits.data(), sizeof(sell::BSplitDesc) * splits.size(), hipMemcpyHostToDevice));
   B->host_mats.resize((size_t)count);
@@ -673,12 +648,11 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
     m.nrows = hs[b]->nrows;
   }
 
-  // capture the single persistent launch once
+  // capture the batched launch once
   sell::BatchArgs a{};
   a.mats = B->mats;
   a.units = B->units;
-  a.slice = B->slice;
-  a.nwaves = B->nwaves;
+  a.nunits = B->nunits;
   a.splits = B->splits;
   a.nsplit = B->nsplit;
   a.partial = B->partial;
@@ -687,7 +661,7 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   SELL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t le = sell::launch_batch(B->combo, B->C, B->U, a, B->grid_blocks, cap);
+    hipError_t le = sell::launch_batch(B->combo, B->C, B->U, a, cap);
     e = hipStreamEndCapture(cap, &B->graph);
     if (le != hipSuccess) e = le;
   }

@@ -34,7 +34,7 @@ struct SplitDesc {
   int64_t poff;
 };
 
-// Work unit of the batched persistent kernel (adds the matrix index).
+// Work unit of the batched kernel (adds the matrix index).
 struct BUnit {
   int32_t mat;
   int32_t item;
@@ -112,9 +112,8 @@ struct BSplitDesc {
 
 struct BatchArgs {
   const BatchMat *mats;
-  const BUnit *units;
-  const int32_t *slice;  // nwaves + 1 unit offsets
-  int32_t nwaves;
+  const BUnit *units;   // one per wave
+  int64_t nunits;
   const BSplitDesc *splits;
   int64_t nsplit;
   void *partial;
@@ -135,8 +134,7 @@ enum DtypeCombo {
 // skip_zero: slots holding value 0 skip their gather (for padding-heavy layouts).
 hipError_t launch_spmv(int combo, int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
-hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, int grid_blocks, hipStream_t s);
-int batch_waves_per_cu(int combo, int C, int U);
+hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, hipStream_t s);
 
 // Build kernels.
 hipError_t build_rowlen(const int64_t *rpt, int64_t n, int64_t nnz, int32_t *len, uint32_t *flags,

@@ -6,8 +6,7 @@ namespace sell {
 hipError_t launch_spmv_f32_f32(int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s) {
   return dev::launch_spmv_t<COMBO_F32_F32>(C, U, V, skip_zero, a, s);
 }
-hipError_t launch_batch_f32_f32(int C, int U, const BatchArgs &a, int grid_blocks, hipStream_t s) {
-  return dev::launch_batch_t<COMBO_F32_F32>(C, U, a, grid_blocks, s);
+hipError_t launch_batch_f32_f32(int C, int U, const BatchArgs &a, hipStream_t s) {
+  return dev::launch_batch_t<COMBO_F32_F32>(C, U, a, s);
 }
-int batch_waves_per_cu_f32_f32(int C, int U) { return dev::batch_waves_per_cu_t<COMBO_F32_F32>(C, U); }
 }  // namespace sell

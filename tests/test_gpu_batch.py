@@ -1,4 +1,4 @@
-"""One persistent hipGraph-captured launch over many matrices of uneven
+"""One hipGraph-captured launch over many matrices of uneven
 size: each result against the oracle."""
 import numpy as np
 import pytest
