@@ -151,7 +151,7 @@ def cold_time(fn, flush, reps: int = 21) -> float:
     return ts[len(ts) // 2] * 1e-3
 
 
-def run_forms(args) -> dict:
+def run_forms(args, probes) -> dict:
     import torch
     import numpy as np
     import synth
@@ -220,7 +220,10 @@ def run_forms(args) -> dict:
         t = time_calls(lambda: sellcs.sell_spmv(h, x, y), max(20, args.steps // 5), 5)
         t_cold = cold_time(lambda: sellcs.sell_spmv(h, x, y), flush)
         pl["C%d_sigma%d" % (C, s)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(h.info["beta"], 4),
-                                      "cold_gfs": round(2.0 * A.nnz / t_cold * 1e-9, 2)}
+                                      "cold_gfs": round(2.0 * A.nnz / t_cold * 1e-9, 2),
+                                      # one x gather per nonzero, against the random-gather probe
+                                      "frac_of_gather_probe": round(8.0 * A.nnz / t * 1e-9 / probes["gather_16mib_gbs"],
+                                                                    4)}
         h.close()
     # reduced-precision storage at the globally sorted layout
     xf = x.float()
@@ -360,7 +363,11 @@ def main():
         return
 
     probes = {"read_gbs": round(sellcs.sell_probe_bandwidth(0, 4 << 30, 10), 1),
-              "copy_gbs": round(sellcs.sell_probe_bandwidth(1, 4 << 30, 10), 1)}
+              "copy_gbs": round(sellcs.sell_probe_bandwidth(1, 4 << 30, 10), 1),
+              # random 8-byte gathers (8 B counted per gather) over arrays the
+              # size of the power-law x (16 MiB) and far beyond the MALL
+              "gather_16mib_gbs": round(sellcs.sell_probe_bandwidth(2, 16 << 20, 5), 1),
+              "gather_2gib_gbs": round(sellcs.sell_probe_bandwidth(2, 2 << 30, 5), 1)}
 
     sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup)
     gfs = 2.0 * A.nnz / sec * 1e-9
@@ -421,7 +428,7 @@ def main():
     h.close()
     del r, c, v
     if not args.no_forms:
-        line["forms"] = run_forms(args)
+        line["forms"] = run_forms(args, probes)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, x_np, C=HEADLINE["C"], sigma=HEADLINE["sigma"])
     print(json.dumps(line))

@@ -71,8 +71,9 @@ typedef struct {
   sell_dtype val_dtype; /* storage of the matrix values: F64, F32 or BF16 */
   sell_dtype acc_dtype; /* accumulation and y: F64 or F32 (F64 values need F64) */
   int32_t unroll;       /* matrix slots in flight per lane: 0 auto, else 4 or 8 */
-  int32_t vec;          /* consecutive slots (rows) each lane loads at once: 0 auto,
-                           else 1, 2 or 4 (2 and 4 need C <= 64 and vec <= C) */
+  int32_t vec;          /* consecutive slots (rows) each lane loads at once: 0 auto
+                           (2 for F64 values with >= 8 nonzeros per row on average,
+                           else 1), else 1, 2 or 4 (2 and 4 need C <= 64 and vec <= C) */
   int32_t seg_cols;     /* widest chunk one work unit covers, in chunk columns,
                            before the chunk is split across waves (rounded up to
                            a multiple of 64): 0 auto, < 0 never split */
@@ -279,8 +280,14 @@ sell_status sell_autotune(const sell_crs *A, int32_t k,
  * roofline model (Sect. 2.1): kind 0 streams bytes through a read-only sum
  * (the "reduction" benchmark), kind 1 copies bytes/2 to another bytes/2
  * buffer (the "copy" benchmark; no write-allocate factor on this device).
+ * kind 2 is the random-gather rate: 2^27 loads of 8 bytes at hashed
+ * positions of an array of the largest power-of-two size <= bytes (the
+ * x-vector accesses of a matrix without column locality); *gbs is then
+ * 8 bytes x gathers / time, so gathers per second = *gbs / 8 x 1e9.
  * Runs reps timed passes after one warm-up on stream; *gbs receives the mean
  * bandwidth in GB/s (1e9 bytes). Allocates and frees its own buffers.
+ * Errors: SELL_ERR_INVALID_ARG for kind outside 0..2, reps < 1 or bytes
+ * below 1 MiB; SELL_ERR_OOM when the buffers cannot be allocated.
  */
 sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps,
                                  void *stream, double *gbs);

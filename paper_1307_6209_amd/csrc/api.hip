@@ -140,10 +140,13 @@ ItemCols item_cols(const std::vector<int32_t> &cl, const Geom &g) {
 }
 
 // Slots per lane when the caller leaves it open: two for FP64 values (one
-// 16-byte access), one for FP32 and BF16 values (measured fastest on the
-// 27-point stencil).
-int default_vec(int C, sell_dtype v) {
-  int V = v == SELL_F64 ? 2 : 1;
+// 16-byte access) unless rows are short, one for FP32 and BF16 values.
+// Measured: FP64 with V = 2 is faster on the 27-point stencil (26.7 nonzeros
+// per row) and on long rows, V = 1 on the power-law matrix (4.2 per row),
+// whose many one- and two-column chunks leave most lanes of a 4-column step
+// idle.
+int default_vec(int C, sell_dtype v, int64_t nnz, int64_t nrows) {
+  int V = v == SELL_F64 && nnz >= 8 * nrows ? 2 : 1;
   if (C > 64) return 1;
   while (V > C) V >>= 1;
   return V;
@@ -218,7 +221,7 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
   h->nnz = A->nnz;
   h->C = C;
   h->sigma = sigma;
-  h->g = sell::geom_of(C, o.vec ? o.vec : default_vec(C, o.val_dtype));
+  h->g = sell::geom_of(C, o.vec ? o.vec : default_vec(C, o.val_dtype, A->nnz, A->nrows));
   h->vdt = o.val_dtype;
   h->adt = o.acc_dtype;
   h->xdt = o.val_dtype == SELL_F64 ? SELL_F64 : SELL_F32;
@@ -885,17 +888,25 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
 // Bandwidth probes
 // ===========================================================================
 extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps, void *stream, double *gbs) {
-  if (!gbs || reps < 1 || (kind != 0 && kind != 1) || bytes < (1u << 20))
+  if (!gbs || reps < 1 || kind < 0 || kind > 2 || bytes < (1u << 20))
     return fail(SELL_ERR_INVALID_ARG, "sell_probe_bandwidth: bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   bytes = bytes / 64 * 64;
   Temp tmp(Mem{});
-  void *a = tmp.get(kind == 0 ? bytes : bytes / 2);
+  const size_t abytes = kind == 1 ? bytes / 2 : bytes;
+  void *a = tmp.get(abytes);
   void *b = kind == 1 ? tmp.get(bytes / 2) : nullptr;
   double *sink = static_cast<double *>(tmp.get(sizeof(double) * 256 * 16));
   if (!a || !sink || (kind == 1 && !b)) return fail(SELL_ERR_OOM, "sell_probe_bandwidth: buffers");
-  SELL_HIP(hipMemsetAsync(a, 0, kind == 0 ? bytes : bytes / 2, s));
-  auto run = [&]() { return kind == 0 ? sell::probe_read(a, bytes, sink, s) : sell::probe_copy(a, b, bytes / 2, s); };
+  SELL_HIP(hipMemsetAsync(a, 0, abytes, s));
+  int64_t moved = (int64_t)bytes;  // bytes counted per pass
+  auto run = [&]() {
+    if (kind == 0) return sell::probe_read(a, bytes, sink, s);
+    if (kind == 1) return sell::probe_copy(a, b, bytes / 2, s);
+    hipError_t e = hipSuccess;
+    moved = sell::probe_gather(a, bytes, sink, s, &e) * (int64_t)sizeof(double);
+    return e;
+  };
   SELL_HIP(run());
   hipEvent_t e0, e1;
   SELL_HIP(hipEventCreate(&e0));
@@ -914,7 +925,7 @@ extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail("sell_probe_bandwidth", err);
-  *gbs = (double)bytes * reps / (total_ms * 1e-3) * 1e-9;
+  *gbs = (double)moved * reps / (total_ms * 1e-3) * 1e-9;
   return SELL_OK;
 }
 

@@ -1,7 +1,9 @@
 // Bandwidth microbenchmarks that set the roofline bandwidth b of the
 // performance model (Sect. 2.1 of Kreutzer et al., arXiv:1307.6209): a
 // read-only sum over an array (the paper's "reduction" benchmark) and an
-// array copy, both with 16-byte non-temporal accesses.
+// array copy, both with 16-byte non-temporal accesses; and a random-gather
+// rate (8-byte loads at hashed positions of an array), the ceiling of
+// products whose right-hand-side accesses have no locality.
 #include "sell_internal.h"
 
 namespace sell {
@@ -50,6 +52,34 @@ __global__ void __launch_bounds__(kBlock) k_copy(const d2 *__restrict__ a, d2 *_
     __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
 }
 
+// 32-bit integer hash "lowbias32" (C. Wellons, hash-prospector): position
+// generator of the gather probe, so no index array is streamed.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Each lane loads per_lane doubles at hashed positions of a (n = mask + 1
+// elements, a power of two), eight loads in flight; plain (cached) loads,
+// as the x gathers of the product.
+__global__ void __launch_bounds__(kBlock) k_gather(const double *__restrict__ a, uint32_t mask, int32_t per_lane,
+                                                   double *sink) {
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  double s = 0.0;
+  for (int32_t i = 0; i < per_lane; i += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a[lowbias32(t * (uint32_t)per_lane + (uint32_t)(i + u)) & mask];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  if (threadIdx.x == 0 || s != s) sink[blockIdx.x] = s;
+}
+
 }  // namespace
 
 constexpr int kProbeBlocks = 256 * 16;
@@ -61,6 +91,17 @@ hipError_t probe_read(const void *a, size_t bytes, double *sink, hipStream_t s) 
   hipLaunchKernelGGL(k_read, dim3((unsigned)(waves * 64 / kBlock)), dim3(kBlock), 0, s, static_cast<const d2 *>(a), n2,
                      per_wave, sink);
   return hipGetLastError();
+}
+
+int64_t probe_gather(const void *a, size_t bytes, double *sink, hipStream_t s, hipError_t *err) {
+  uint32_t mask = 1;
+  while ((uint64_t)(mask + 1) * 2 * sizeof(double) <= bytes && mask < 0x7fffffffu) mask = mask * 2 + 1;
+  constexpr int32_t kPerLane = 256;
+  constexpr int kBlocks = 2048;  // 524,288 lanes x 256 loads = 2^27 gathers
+  hipLaunchKernelGGL(k_gather, dim3(kBlocks), dim3(kBlock), 0, s, static_cast<const double *>(a), mask, kPerLane,
+                     sink);
+  *err = hipGetLastError();
+  return (int64_t)kBlocks * kBlock * kPerLane;
 }
 
 hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s) {

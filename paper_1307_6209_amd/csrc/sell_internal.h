@@ -163,6 +163,9 @@ hipError_t launch_crs(const int64_t *rpt, const int32_t *col, const double *val,
 // Bandwidth probes.
 hipError_t probe_read(const void *a, size_t bytes, double *sink, hipStream_t s);
 hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s);
+// Launches 2^27 random 8-byte gathers over the largest power-of-two prefix
+// of a (bytes); returns the gather count.
+int64_t probe_gather(const void *a, size_t bytes, double *sink, hipStream_t s, hipError_t *err);
 
 }  // namespace sell
 

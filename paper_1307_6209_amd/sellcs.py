@@ -394,7 +394,8 @@ def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=
 
 
 def sell_probe_bandwidth(kind: int, nbytes: int, reps: int = 10, stream=None) -> float:
-    """Read-only (kind 0) or copy (kind 1) bandwidth in GB/s."""
+    """Read-only (kind 0) or copy (kind 1) bandwidth in GB/s; kind 2: random
+    8-byte gathers over an nbytes array, in gathered GB/s (8 B per gather)."""
     g = c_d()
     _check(lib().sell_probe_bandwidth(kind, nbytes, reps, _stream(stream), ctypes.byref(g)), "sell_probe_bandwidth")
     return g.value

@@ -16,6 +16,18 @@ def test_probes_plausible():
     assert 1000 < c < 8000 * 1.02
 
 
+def test_gather_probe_plausible():
+    """Random 8-byte gathers: a small (L2-sized) array serves them faster than
+    one far beyond the 256 MB MALL, and neither beats the streaming read."""
+    from paper_1307_6209_amd import sellcs
+    small = sellcs.sell_probe_bandwidth(2, 2 << 20, 3)
+    big = sellcs.sell_probe_bandwidth(2, 2 << 30, 3)
+    read = sellcs.sell_probe_bandwidth(0, 2 << 30, 3)
+    say("gather GB/s (8 B per gather): 2 MiB", small, "2 GiB", big, "read", read)
+    assert 0 < big < small
+    assert big < read
+
+
 def test_autotune_small():
     from paper_1307_6209_amd import sellcs
     A = synth.powerlaw(100_000, seed=71)
