@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a few products and one copy probe")
     ap.add_argument("--sigma-sweep", action="store_true", help="SELL-32-sigma sweep on the power-law matrix")
+    ap.add_argument("--probe-sweep", action="store_true",
+                    help="random-gather probe over array sizes 1 MiB .. 4 GiB, and the read probe")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the SELL-C-sigma product here is a single-device kernel "
@@ -341,6 +343,13 @@ def main():
     torch.cuda.set_device(0)
     if args.sigma_sweep:
         sigma_sweep(args)
+        return
+    if args.probe_sweep:
+        res = {"read_4gib_gbs": round(sellcs.sell_probe_bandwidth(0, 4 << 30, 10), 1)}
+        for mib in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 4096):
+            g = sellcs.sell_probe_bandwidth(2, mib << 20, 5)
+            res["gather_%dmib_ggather_per_s" % mib] = round(g / 8.0, 1)
+        print(json.dumps({"probe_sweep": res}))
         return
     A = synth.workload(HEADLINE["workload"])
     x_np = synth.uniform(A.ncols, synth.SEED_X + 2)
