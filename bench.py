@@ -202,12 +202,25 @@ def run_forms(args, probes) -> dict:
         t_seq = time_calls(lambda: [sellcs.sell_spmv(hh, xx, yy) for hh, xx, yy in zip(hs, xs, ys)],
                            max(5, args.steps // 50), 2)
         t_cold = cold_time(lambda: sellcs.sell_batch_spmv(b, xs, ys), flush)
+        bp = sellcs.sell_batch_create_persistent(hs)
+        t_pers = time_calls(lambda: sellcs.sell_batch_spmv(bp, xs, ys), max(10, args.steps // 10), 3)
         out["batch64_%s" % tag] = {"gfs": round(2.0 * nnz / t * 1e-9, 2), "us": round(t * 1e6, 2),
                                    "separate_launches_us": round(t_seq * 1e6, 2),
-                                   "cold_gfs": round(2.0 * nnz / t_cold * 1e-9, 2)}
+                                   "cold_gfs": round(2.0 * nnz / t_cold * 1e-9, 2),
+                                   "persistent_us": round(t_pers * 1e6, 2)}
+        bp.close()
         b.close()
         for hh in hs:
             hh.close()
+    # one C for the batch and a sigma per matrix, chosen by the batch autotuner
+    tb = sellcs.sell_batch_autotune([(rr, cc, vv, B.ncols) for (rr, cc, vv), B in zip(devs, mats)],
+                                    C=(16, 32, 64), sigma=(1, 64, 1024, 1 << 40), reps=20)
+    hist = {}
+    for sg in tb["sigmas"]:
+        key = "all rows" if sg >= 1 << 40 else str(sg)
+        hist[key] = hist.get(key, 0) + 1
+    out["batch64_autotuned"] = {"C": tb["C"], "gfs": round(tb["gflops"], 2), "us": round(tb["us_per_call"], 2),
+                                "sigma_counts": hist, "candidates": tb["candidates"]}
     del devs
     # power-law n = 2,000,000: plain and globally sorted
     A = synth.workload("powerlaw_2m")

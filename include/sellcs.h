@@ -201,6 +201,19 @@ sell_status sell_batch_create(const sell_handle *hs, int32_t count,
                               sell_batch *out);
 
 /*
+ * sell_batch_create_persistent -- the same batch as one persistent launch:
+ * the grid is the number of wavefronts the device holds at once, and the
+ * units are cut into slices of equal estimated cost (wave steps plus a fixed
+ * charge per unit), one slice per wavefront, run back to back. Same
+ * arguments, ownership, errors and results as sell_batch_create; use it with
+ * sell_batch_spmv and sell_batch_destroy. (One wavefront per unit, the
+ * sell_batch_create form, measured faster on uneven power-law batches: the
+ * hardware dispatcher balances better than the static estimate.)
+ */
+sell_status sell_batch_create_persistent(const sell_handle *hs, int32_t count,
+                                         sell_batch *out);
+
+/*
  * sell_batch_spmv -- ys[b] = A_b xs[b] for every matrix of the batch, as one
  * graph launch on stream (asynchronous). xs and ys are host arrays of count
  * device pointers. When they differ from the previous call, the device copy
@@ -274,6 +287,35 @@ typedef struct {
 sell_status sell_autotune(const sell_crs *A, int32_t k,
                           const sell_tune_space *space, void *stream,
                           sell_tuned *best);
+
+/* Result of sell_batch_autotune. */
+typedef struct {
+  int32_t C;            /* chunk height of the fastest batch */
+  int32_t candidates;   /* batches timed (one per C that every matrix supports) */
+  double gflops;        /* useful GF/s of the batch: 2 * (sum of nnz) / time */
+  double us_per_call;   /* one batched launch (sell_batch_create form) */
+} sell_batch_tuned;
+
+/*
+ * sell_batch_autotune -- choose one chunk height for a batch of count
+ * matrices (As: host array of device CRS descriptions, borrowed) and a
+ * sigma for each matrix. For every C of space->C (default 16, 32, 64) each
+ * matrix takes the sigma of space->sigma (default 1, 1024 and one window
+ * over all rows) whose layout moves the fewest bytes under the code-balance
+ * model (Sect. 4, alpha at its ideal value: padded matrix plus the
+ * permutation read when sigma > 1), found by layout-only builds; the batch of
+ * those matrices is then built, launched reps times (space->reps, default 20)
+ * and timed. Uses space->val_dtype and space->acc_dtype; the other fields of
+ * space are ignored. *best receives the fastest C and sigma_out (host,
+ * count entries) the sigma each matrix had in that batch. Synchronous on
+ * stream; temporary device memory for the vectors and the trial builds.
+ * Errors: SELL_ERR_INVALID_ARG for null arguments or count < 1; the errors
+ * of sell_build for a malformed matrix; SELL_ERR_UNSUPPORTED when no C of the
+ * space suits every matrix.
+ */
+sell_status sell_batch_autotune(const sell_crs *As, int32_t count,
+                                const sell_tune_space *space, void *stream,
+                                sell_batch_tuned *best, int64_t *sigma_out);
 
 /*
  * sell_probe_bandwidth -- achievable device memory bandwidth b of the

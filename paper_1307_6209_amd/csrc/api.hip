@@ -535,8 +535,11 @@ struct sell_batch_s {
   Geom g{};
   int32_t seg_cols = 0;
   int64_t nunits = 0, nsplit = 0;
+  bool persistent = false;
+  int32_t nwaves = 0;  // persistent form only
   sell::BatchMat *mats = nullptr;
   sell::BUnit *units = nullptr;
+  int32_t *slice = nullptr;  // persistent form only
   sell::BSplitDesc *splits = nullptr;
   void *partial = nullptr;
   std::vector<sell::BatchMat> host_mats;
@@ -567,7 +570,9 @@ void *batch_alloc(sell_batch_s *b, size_t bytes) {
 
 }  // namespace
 
-extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, sell_batch *out) {
+namespace {
+
+sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persistent, sell_batch *out) {
   if (!hs || !out || count < 1) return fail(SELL_ERR_INVALID_ARG, "sell_batch_create: bad arguments");
   *out = nullptr;
   for (int32_t b = 0; b < count; ++b)
@@ -627,13 +632,44 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   B->nsplit = (int64_t)splits.size();
   if (B->nunits >= ((int64_t)1 << 31)) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_create: too many work units");
 
+  // persistent form: one slice of equal estimated cost (wave steps plus a
+  // fixed charge per unit) for each resident wave
+  std::vector<int32_t> slice;
+  if (persistent) {
+    const int wpcu = std::max(1, sell::batch_waves_per_cu(B->combo, B->C, B->U));
+    int64_t nwaves = std::max<int64_t>(4, std::min<int64_t>((int64_t)di.cus * wpcu, B->nunits));
+    nwaves = (nwaves + 3) / 4 * 4;
+    const int64_t kFixed = 4;
+    std::vector<int64_t> cost(units.size());
+    int64_t tot_cost = 0;
+    for (size_t q = 0; q < units.size(); ++q) {
+      const sell::BUnit &u = units[q];
+      const int64_t w = st[u.mat].cols[(size_t)u.item];
+      const int64_t cols = u.nseg > 1 ? std::min<int64_t>(S, w - (int64_t)u.seg * S) : w;
+      cost[q] = (cols + g.T - 1) / g.T + kFixed;
+      tot_cost += cost[q];
+    }
+    slice.assign((size_t)nwaves + 1, (int32_t)B->nunits);
+    slice[0] = 0;
+    int64_t acc = 0, w = 1;
+    for (size_t q = 0; q < units.size() && w < nwaves; ++q) {
+      acc += cost[q];
+      while (w < nwaves && acc * nwaves >= w * tot_cost) slice[(size_t)w++] = (int32_t)(q + 1);
+    }
+    B->persistent = true;
+    B->nwaves = (int32_t)nwaves;
+  }
+
   B->mats = static_cast<sell::BatchMat *>(batch_alloc(B.get(), sizeof(sell::BatchMat) * (size_t)count));
   B->units = static_cast<sell::BUnit *>(batch_alloc(B.get(), sizeof(sell::BUnit) * std::max<size_t>(1, units.size())));
   B->splits = static_cast<sell::BSplitDesc *>(
       batch_alloc(B.get(), sizeof(sell::BSplitDesc) * std::max<size_t>(1, splits.size())));
   B->partial = batch_alloc(B.get(), sizeof(double) * (size_t)std::max<int64_t>(1, off));
-  if (!B->mats || !B->units || !B->splits || !B->partial)
+  if (persistent) B->slice = static_cast<int32_t *>(batch_alloc(B.get(), sizeof(int32_t) * slice.size()));
+  if (!B->mats || !B->units || !B->splits || !B->partial || (persistent && !B->slice))
     return fail(SELL_ERR_OOM, "sell_batch_create: allocation failed");
+  if (persistent)
+    SELL_HIP(hipMemcpy(B->slice, slice.data(), sizeof(int32_t) * slice.size(), hipMemcpyHostToDevice));
   if (!units.empty())
     SELL_HIP(hipMemcpy(B->units, units.data(), sizeof(sell::BUnit) * units.size(), hipMemcpyHostToDevice));
   if (!splits.empty())
@@ -656,6 +692,8 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   a.mats = B->mats;
   a.units = B->units;
   a.nunits = B->nunits;
+  a.slice = B->slice;
+  a.nwaves = B->nwaves;
   a.splits = B->splits;
   a.nsplit = B->nsplit;
   a.partial = B->partial;
@@ -674,6 +712,16 @@ extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, s
   guard.armed = false;
   *out = B.release();
   return SELL_OK;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_batch_create(const sell_handle *hs, int32_t count, sell_batch *out) {
+  return batch_create_impl(hs, count, false, out);
+}
+
+extern "C" sell_status sell_batch_create_persistent(const sell_handle *hs, int32_t count, sell_batch *out) {
+  return batch_create_impl(hs, count, true, out);
 }
 
 extern "C" sell_status sell_batch_spmv(sell_batch b, const void *const *xs, void *const *ys, void *stream) {
@@ -887,6 +935,127 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
 // ===========================================================================
 // Bandwidth probes
 // ===========================================================================
+extern "C" sell_status sell_batch_autotune(const sell_crs *As, int32_t count, const sell_tune_space *space,
+                                           void *stream, sell_batch_tuned *best, int64_t *sigma_out) {
+  if (!As || count < 1 || !best || !sigma_out) return fail(SELL_ERR_INVALID_ARG, "sell_batch_autotune: bad arguments");
+  const int32_t defC[] = {16, 32, 64};
+  const int64_t defS[] = {1, 1024, (int64_t)1 << 40};
+  sell_tune_space sp{};
+  if (space) sp = *space;
+  const int32_t *Cs = sp.nC > 0 ? sp.C : defC;
+  const int nC = sp.nC > 0 ? sp.nC : 3;
+  const int64_t *Ss = sp.nsigma > 0 ? sp.sigma : defS;
+  const int nS = sp.nsigma > 0 ? sp.nsigma : 3;
+  const int reps = sp.reps > 0 ? sp.reps : 20;
+  sell_build_opts o{};
+  o.val_dtype = sp.val_dtype;
+  o.acc_dtype = sp.acc_dtype;
+  if (combo_of(o.val_dtype, o.acc_dtype) < 0) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_autotune: dtype pair");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // one x and one y per matrix, carved from two buffers (offsets rounded to
+  // 32 elements)
+  const size_t xs = o.val_dtype == SELL_F64 ? 8 : 4, ys = o.acc_dtype == SELL_F64 ? 8 : 4;
+  std::vector<size_t> xoff(count), yoff(count);
+  size_t xtot = 0, ytot = 0;
+  int64_t nnz = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    xoff[b] = xtot;
+    yoff[b] = ytot;
+    xtot += (size_t)(std::max<int64_t>(As[b].ncols, 1) + 31) / 32 * 32;
+    ytot += (size_t)(std::max<int64_t>(As[b].nrows, 1) + 31) / 32 * 32;
+    nnz += As[b].nnz;
+  }
+  Temp tmp(Mem{});
+  char *x = static_cast<char *>(tmp.get(xs * xtot));
+  char *y = static_cast<char *>(tmp.get(ys * ytot));
+  if (!x || !y) return fail(SELL_ERR_OOM, "sell_batch_autotune: vectors");
+  SELL_HIP(hipMemsetAsync(x, 0, xs * xtot, s));
+  std::vector<const void *> xp(count);
+  std::vector<void *> yp(count);
+  for (int32_t b = 0; b < count; ++b) {
+    xp[b] = x + xs * xoff[b];
+    yp[b] = y + ys * yoff[b];
+  }
+  hipEvent_t e0, e1;
+  SELL_HIP(hipEventCreate(&e0));
+  SELL_HIP(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } ev{e0, e1};
+  // handles and batch of one candidate, released on every exit
+  struct Trial {
+    std::vector<sell_handle> hs;
+    sell_batch bt = nullptr;
+    void clear() {
+      if (bt) sell_batch_destroy(bt);
+      bt = nullptr;
+      for (sell_handle h : hs) sell_destroy(h);
+      hs.clear();
+    }
+    ~Trial() { clear(); }
+  } trial;
+
+  const double sv = (double)dtype_size(o.val_dtype);
+  sell_batch_tuned r{};
+  r.gflops = -1.0;
+  std::vector<int64_t> sig(count), best_sig(count);
+  for (int ic = 0; ic < nC; ++ic) {
+    const int32_t C = Cs[ic];
+    bool ok = true;
+    for (int32_t b = 0; b < count && ok; ++b) {
+      double best_bytes = -1.0;
+      for (int is = 0; is < nS; ++is) {
+        sell_handle h = nullptr;
+        sell_status st = build_impl(&As[b], C, Ss[is], &o, stream, &h, true);
+        if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
+        if (st != SELL_OK) return st;
+        const double bytes = (sv + 4.0) * (double)h->padded + (h->perm ? 4.0 * (double)h->nrows : 0.0);
+        if (best_bytes < 0 || bytes < best_bytes) {
+          best_bytes = bytes;
+          sig[b] = Ss[is];
+        }
+        sell_destroy(h);
+      }
+      if (best_bytes < 0) ok = false;
+    }
+    if (!ok) continue;
+    trial.hs.assign(count, nullptr);
+    for (int32_t b = 0; b < count; ++b) {
+      sell_status st = sell_build(&As[b], C, sig[b], &o, stream, &trial.hs[b]);
+      if (st != SELL_OK) return st;
+    }
+    sell_status st = sell_batch_create(trial.hs.data(), count, &trial.bt);
+    if (st != SELL_OK) return st;
+    for (int w = 0; w < 3 && st == SELL_OK; ++w) st = sell_batch_spmv(trial.bt, xp.data(), yp.data(), stream);
+    if (st != SELL_OK) return st;
+    (void)hipEventRecord(e0, s);
+    for (int q = 0; q < reps; ++q) (void)sell_batch_spmv(trial.bt, xp.data(), yp.data(), stream);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return hip_fail("sell_batch_autotune: timing", hipGetLastError());
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double t = (double)ms * 1e-3 / reps;
+    const double gf = t > 0 ? 2.0 * (double)nnz / t * 1e-9 : 0.0;
+    ++r.candidates;
+    if (gf > r.gflops) {
+      r.C = C;
+      r.gflops = gf;
+      r.us_per_call = t * 1e6;
+      best_sig = sig;
+    }
+    trial.clear();
+  }
+  if (r.candidates == 0) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_autotune: no C suits every matrix");
+  for (int32_t b = 0; b < count; ++b) sigma_out[b] = best_sig[b];
+  *best = r;
+  return SELL_OK;
+}
+
 extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps, void *stream, double *gbs) {
   if (!gbs || reps < 1 || kind < 0 || kind > 2 || bytes < (1u << 20))
     return fail(SELL_ERR_INVALID_ARG, "sell_probe_bandwidth: bad arguments");

@@ -5,7 +5,8 @@ namespace sell {
 
 #define SELL_DECL(lc)                                                                 \
   hipError_t launch_spmv_##lc(int C, int U, int V, bool sz, const SpmvArgs &a, hipStream_t s);      \
-  hipError_t launch_batch_##lc(int C, int U, const BatchArgs &a, hipStream_t s);
+  hipError_t launch_batch_##lc(int C, int U, const BatchArgs &a, hipStream_t s); \
+  int batch_waves_per_cu_##lc(int C, int U);
 SELL_DECL(f64_f64)
 SELL_DECL(f32_f32)
 SELL_DECL(f32_f64)
@@ -33,6 +34,17 @@ hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, hipStream_t
     case COMBO_BF16_F64: return launch_batch_bf16_f64(C, U, a, s);
   }
   return hipErrorInvalidValue;
+}
+
+int batch_waves_per_cu(int combo, int C, int U) {
+  switch (combo) {
+    case COMBO_F64_F64: return batch_waves_per_cu_f64_f64(C, U);
+    case COMBO_F32_F32: return batch_waves_per_cu_f32_f32(C, U);
+    case COMBO_F32_F64: return batch_waves_per_cu_f32_f64(C, U);
+    case COMBO_BF16_F32: return batch_waves_per_cu_bf16_f32(C, U);
+    case COMBO_BF16_F64: return batch_waves_per_cu_bf16_f64(C, U);
+  }
+  return 4;
 }
 
 // Block form (FP64 only): C in {8, ..., 128}, KV in {1, 2, 4, 8}.

@@ -112,8 +112,10 @@ struct BSplitDesc {
 
 struct BatchArgs {
   const BatchMat *mats;
-  const BUnit *units;   // one per wave
+  const BUnit *units;
   int64_t nunits;
+  const int32_t *slice;  // persistent form: nwaves + 1 unit offsets; nullptr: one unit per wave
+  int32_t nwaves;
   const BSplitDesc *splits;
   int64_t nsplit;
   void *partial;
@@ -135,6 +137,8 @@ enum DtypeCombo {
 hipError_t launch_spmv(int combo, int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, hipStream_t s);
+// Resident waves per CU of the batched kernel (persistent grid size).
+int batch_waves_per_cu(int combo, int C, int U);
 
 // Build kernels.
 hipError_t build_rowlen(const int64_t *rpt, int64_t n, int64_t nnz, int32_t *len, uint32_t *flags,

@@ -9,4 +9,5 @@ hipError_t launch_spmv_bf16_f32(int C, int U, int V, bool skip_zero, const SpmvA
 hipError_t launch_batch_bf16_f32(int C, int U, const BatchArgs &a, hipStream_t s) {
   return dev::launch_batch_t<COMBO_BF16_F32>(C, U, a, s);
 }
+int batch_waves_per_cu_bf16_f32(int C, int U) { return dev::batch_waves_per_cu_t<COMBO_BF16_F32>(C, U); }
 }  // namespace sell

@@ -9,4 +9,5 @@ hipError_t launch_spmv_f32_f64(int C, int U, int V, bool skip_zero, const SpmvAr
 hipError_t launch_batch_f32_f64(int C, int U, const BatchArgs &a, hipStream_t s) {
   return dev::launch_batch_t<COMBO_F32_F64>(C, U, a, s);
 }
+int batch_waves_per_cu_f32_f64(int C, int U) { return dev::batch_waves_per_cu_t<COMBO_F32_F64>(C, U); }
 }  // namespace sell

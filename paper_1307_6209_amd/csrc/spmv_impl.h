@@ -283,19 +283,30 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
 }
 
 // Batched form: one launch over the concatenated work units of all
-// matrices, one unit per wave (the hardware dispatcher balances the uneven
-// matrices; a persistent form with equal-cost slices per resident wave was
-// measured slower).
+// matrices. Default: one unit per wave (the hardware dispatcher balances the
+// uneven matrices). Persistent form (slice != nullptr): a grid of resident
+// waves, wave w running units [slice[w], slice[w+1]) back to back.
 template <int COMBO, int C, int U>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (w >= a.nunits) return;
-  const BUnit u = a.units[w];
-  const BatchMat m = a.mats[u.mat];
-  const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
-  spmv_unit<COMBO, C, U, 1, true>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg, poff,
-                                  a.partial, a.seg_cols, lane);
+  int64_t q0, q1;
+  if (a.slice) {
+    if (w >= a.nwaves) return;
+    q0 = a.slice[w];
+    q1 = a.slice[w + 1];
+  } else {
+    if (w >= a.nunits) return;
+    q0 = w;
+    q1 = w + 1;
+  }
+  for (int64_t q = q0; q < q1; ++q) {
+    const BUnit u = a.units[q];
+    const BatchMat m = a.mats[u.mat];
+    const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
+    spmv_unit<COMBO, C, U, 1, true>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg,
+                                    poff, a.partial, a.seg_cols, lane);
+  }
 }
 
 template <int COMBO, int C>
@@ -498,7 +509,8 @@ hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a
 template <int COMBO>
 hipError_t launch_batch_t(int C, int U, const BatchArgs &a, hipStream_t s) {
   if (a.nunits <= 0) return hipSuccess;
-  const unsigned nb = (unsigned)((a.nunits + kWavesPerBlock - 1) / kWavesPerBlock);
+  const int64_t waves = a.slice ? a.nwaves : a.nunits;
+  const unsigned nb = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
 #define SELL_L(CC, UU)                                                                                     \
   if (C == CC && U == UU) {                                                                               \
     hipLaunchKernelGGL((k_batch<COMBO, CC, UU>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);           \
@@ -511,6 +523,21 @@ hipError_t launch_batch_t(int C, int U, const BatchArgs &a, hipStream_t s) {
   SELL_FOR_EACH_CU(SELL_L)
 #undef SELL_L
   return hipErrorInvalidValue;
+}
+
+template <int COMBO>
+int batch_waves_per_cu_t(int C, int U) {
+  int blocks = 0;
+#define SELL_L(CC, UU)                                                                                              \
+  if (C == CC && U == UU) {                                                                                        \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<COMBO, CC, UU>, 64 * kWavesPerBlock, 0) != \
+        hipSuccess)                                                                                                \
+      blocks = 1;                                                                                                  \
+    return blocks * kWavesPerBlock;                                                                                \
+  }
+  SELL_FOR_EACH_CU(SELL_L)
+#undef SELL_L
+  return kWavesPerBlock;
 }
 
 }  // namespace dev

@@ -67,6 +67,10 @@ class SellTuned(ctypes.Structure):
                 ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32), ("predicted", c_i32)]
 
 
+class SellBatchTuned(ctypes.Structure):
+    _fields_ = [("C", c_i32), ("candidates", c_i32), ("gflops", c_d), ("us_per_call", c_d)]
+
+
 # Every entry point the header declares: name -> (restype, argtypes).
 SIGNATURES = {
     "sell_build": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, c_i64, ctypes.POINTER(SellBuildOpts), c_p,
@@ -77,6 +81,9 @@ SIGNATURES = {
     "sell_export": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p, c_p]),
     "sell_destroy": (ctypes.c_int, [c_p]),
     "sell_batch_create": (ctypes.c_int, [ctypes.POINTER(c_p), c_i32, ctypes.POINTER(c_p)]),
+    "sell_batch_create_persistent": (ctypes.c_int, [ctypes.POINTER(c_p), c_i32, ctypes.POINTER(c_p)]),
+    "sell_batch_autotune": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, ctypes.POINTER(SellTuneSpace), c_p,
+                                           ctypes.POINTER(SellBatchTuned), ctypes.POINTER(c_i64)]),
     "sell_batch_spmv": (ctypes.c_int, [c_p, ctypes.POINTER(c_p), ctypes.POINTER(c_p), c_p]),
     "sell_batch_destroy": (ctypes.c_int, [c_p]),
     "sell_autotune": (ctypes.c_int, [ctypes.POINTER(SellCrs), c_i32, ctypes.POINTER(SellTuneSpace), c_p,
@@ -351,9 +358,18 @@ class SellBatch:
 
 
 def sell_batch_create(mats) -> SellBatch:
+    """One graph-captured launch over all matrices, one wave per work unit."""
     arr = (c_p * len(mats))(*[m.handle for m in mats])
     b = c_p()
     _check(lib().sell_batch_create(arr, len(mats), ctypes.byref(b)), "sell_batch_create")
+    return SellBatch(b, mats)
+
+
+def sell_batch_create_persistent(mats) -> SellBatch:
+    """The same batch as one persistent launch (resident waves, equal-cost slices)."""
+    arr = (c_p * len(mats))(*[m.handle for m in mats])
+    b = c_p()
+    _check(lib().sell_batch_create_persistent(arr, len(mats), ctypes.byref(b)), "sell_batch_create_persistent")
     return SellBatch(b, mats)
 
 
@@ -391,6 +407,34 @@ def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=
     r = SellTuned()
     _check(lib().sell_autotune(ctypes.byref(A), k, ctypes.byref(sp), _stream(stream), ctypes.byref(r)), "sell_autotune")
     return {name: getattr(r, name) for name, _ in SellTuned._fields_}
+
+
+def sell_batch_autotune(mats, C=(), sigma=(), val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0,
+                        stream=None) -> dict:
+    """One C for the batch and a sigma per matrix (fewest model bytes), the
+    fastest C by timing the batched launch. mats: list of (rpt, col, val,
+    ncols) device tensors. Returns C, sigmas (per matrix), gflops,
+    us_per_call and candidates."""
+    import torch
+    n = len(mats)
+    arr = (SellCrs * n)()
+    for i, (rpt, col, val, ncols) in enumerate(mats):
+        nnz = col.numel()
+        arr[i] = SellCrs(rpt.numel() - 1, int(ncols), nnz, _dptr(rpt, torch.int64, "rpt"),
+                         _dptr(col, torch.int32, "col"), _dptr(val, torch.float64, "val", nnz))
+    if acc_dtype is None:
+        acc_dtype = "f64" if val_dtype == "f64" else "f32"
+    ca, sa = (c_i32 * len(C))(*C), (c_i64 * len(sigma))(*sigma)
+    empty = (c_i32 * 0)()
+    sp = SellTuneSpace(ca, len(C), sa, len(sigma), empty, 0, empty, 0, empty, 0, empty, 0, DTYPES[val_dtype],
+                       DTYPES[acc_dtype], reps, 0)
+    r = SellBatchTuned()
+    sig = (c_i64 * n)()
+    _check(lib().sell_batch_autotune(arr, n, ctypes.byref(sp), _stream(stream), ctypes.byref(r), sig),
+           "sell_batch_autotune")
+    out = {name: getattr(r, name) for name, _ in SellBatchTuned._fields_}
+    out["sigmas"] = list(sig)
+    return out
 
 
 def sell_probe_bandwidth(kind: int, nbytes: int, reps: int = 10, stream=None) -> float:

@@ -101,10 +101,16 @@ def check_reduced(A, h, x, val_dtype, acc, C, nseg_max=1):
     Against the double product of A and x^:
         |y - A x^|_i <= [u_v + (1 + u_v) gamma_acc(m_i)] (|A||x^|)_i.
     Returns (max componentwise, normwise) error against A x^."""
+    xr = oracle.round_f32(x).astype(np.float64)
+    return check_reduced_y(A, spmv_gpu(h, xr), h, x, val_dtype, acc, C, nseg_max)
+
+
+def check_reduced_y(A, y, h, x, val_dtype, acc, C, nseg_max=1):
+    """The bounds of check_reduced for a result y computed elsewhere (the
+    batched launch) from the layout of handle h."""
     from paper_1307_6209_amd import sellcs
     xr = oracle.round_f32(x).astype(np.float64)
     vr = rounded_values(A, val_dtype)
-    y = spmv_gpu(h, xr)
     yq = oracle.crs_spmv_hi(A, xr, val=vr)
     aq = oracle.crs_absmv(A, xr, val=vr)
     lay = sellcs.sell_export(h)

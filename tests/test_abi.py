@@ -32,7 +32,8 @@ def L():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["sell_build", "sell_spmv", "sell_spmmv", "sell_export", "sell_info", "sell_destroy",
-                 "sell_batch_create", "sell_batch_spmv", "sell_batch_destroy", "sell_autotune",
+                 "sell_batch_create", "sell_batch_create_persistent", "sell_batch_spmv", "sell_batch_destroy",
+                 "sell_autotune", "sell_batch_autotune",
                  "sell_probe_bandwidth", "sell_status_string", "sell_last_error"]:
         assert must in names
 
@@ -79,6 +80,13 @@ def test_host_side_argument_errors(L):
     assert L.sell_spmv(None, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmmv(None, None, None, 4, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_batch_create(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_batch_create_persistent(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    bt = sellcs.SellBatchTuned()
+    sig = (ctypes.c_int64 * 1)()
+    assert L.sell_batch_autotune(None, 1, None, None, ctypes.byref(bt), sig) == sellcs.SELL_ERR_INVALID_ARG
+    crs = (sellcs.SellCrs * 1)()
+    assert L.sell_batch_autotune(crs, 0, None, None, ctypes.byref(bt), sig) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_batch_autotune(crs, 1, None, None, None, sig) == sellcs.SELL_ERR_INVALID_ARG
     g = ctypes.c_double()
     assert L.sell_probe_bandwidth(7, 1 << 30, 1, None, ctypes.byref(g)) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_autotune(None, 1, None, None, None) == sellcs.SELL_ERR_INVALID_ARG

@@ -5,9 +5,17 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import build, check_fp64, check_reduced, say
+from gpu_util import build, check_fp64, check_reduced_y, say
 
 pytestmark = pytest.mark.gpu
+
+# both forms of the batched launch: one wave per unit, and persistent
+FORMS = ["sell_batch_create", "sell_batch_create_persistent"]
+
+
+def create(form, hs):
+    from paper_1307_6209_amd import sellcs
+    return getattr(sellcs, form)(hs)
 
 
 def make_batch(count, seed, lo=1000, hi=20000):
@@ -25,14 +33,15 @@ def run(b, mats, xs, dtype):
     return [y.double().cpu().numpy() for y in yd]
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("C", [16, 32, 64, 128])
-def test_batch_fp64(C):
+def test_batch_fp64(C, form):
     import torch
     from paper_1307_6209_amd import sellcs
     mats = make_batch(12, 3)
     sigmas = [1, C, 256, 4096, 10**9, 1, 512, 1, 2048, C, 1, 100000]
     hs = [build(A, C, s) for A, s in zip(mats, sigmas)]
-    b = sellcs.sell_batch_create(hs)
+    b = create(form, hs)
     xs = [synth.uniform(A.ncols, 50 + i, 1) for i, A in enumerate(mats)]
     say("batch C", C, "rows", sum(A.nrows for A in mats))
     ys = run(b, mats, xs, (torch.float64, torch.float64))
@@ -46,12 +55,13 @@ def test_batch_fp64(C):
     b.close()
 
 
-def test_batch_repeat_same_pointers_is_deterministic():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_repeat_same_pointers_is_deterministic(form):
     import torch
     from paper_1307_6209_amd import sellcs
     mats = make_batch(20, 4, 1000, 50000)
     hs = [build(A, 32, 64) for A in mats]
-    b = sellcs.sell_batch_create(hs)
+    b = create(form, hs)
     xd = [torch.from_numpy(synth.uniform(A.ncols, 9, 1)).cuda() for A in mats]
     yd = [torch.empty(A.nrows, dtype=torch.float64, device="cuda") for A in mats]
     sellcs.sell_batch_spmv(b, xd, yd)
@@ -66,29 +76,32 @@ def test_batch_repeat_same_pointers_is_deterministic():
         check_fp64(A, y, x.cpu().numpy())
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("val_dtype,acc", [("f32", "f32"), ("bf16", "f64")])
-def test_batch_reduced(val_dtype, acc):
+def test_batch_reduced(val_dtype, acc, form):
     import torch
     from paper_1307_6209_amd import sellcs
     mats = make_batch(6, 5)
     hs = [build(A, 32, 128, val_dtype=val_dtype, acc_dtype=acc) for A in mats]
-    b = sellcs.sell_batch_create(hs)
+    b = create(form, hs)
     xs = [oracle.round_f32(synth.uniform(A.ncols, 60 + i, 1)).astype(np.float64) for i, A in enumerate(mats)]
     ys = run(b, mats, xs, (torch.float32, torch.float64 if acc == "f64" else torch.float32))
     for A, h, x, y in zip(mats, hs, xs, ys):
-        # compare with the single-matrix launch, which check_reduced pins to the oracle
-        check_reduced(A, h, x, val_dtype, acc, 32, nseg_max=64)
+        comp, norm = check_reduced_y(A, y, h, x, val_dtype, acc, 32, nseg_max=64)
+        say("batch", form, val_dtype, acc, "componentwise %.3g normwise %.3g" % (comp, norm))
 
 
-def test_batch_mixed_C_rejected():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_mixed_C_rejected(form):
     from paper_1307_6209_amd import sellcs
     mats = make_batch(2, 6)
     hs = [build(mats[0], 32, 1), build(mats[1], 64, 1)]
     with pytest.raises(sellcs.SellError):
-        sellcs.sell_batch_create(hs)
+        create(form, hs)
 
 
-def test_batch_graph_replays_with_eager_work_between():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_graph_replays_with_eager_work_between(form):
     """Replay the captured launch several times with other eager launches and
     synchronisations in between: every replay gives the same bits, and they
     match the oracle."""
@@ -96,7 +109,7 @@ def test_batch_graph_replays_with_eager_work_between():
     from paper_1307_6209_amd import sellcs
     mats = make_batch(10, 7, 1000, 60000)
     hs = [build(A, 32, [1, 64, 4096][i % 3]) for i, A in enumerate(mats)]
-    b = sellcs.sell_batch_create(hs)
+    b = create(form, hs)
     xs = [torch.from_numpy(synth.uniform(A.ncols, 90 + i, 1)).cuda() for i, A in enumerate(mats)]
     ys = [torch.empty(A.nrows, dtype=torch.float64, device="cuda") for A in mats]
     other = build(synth.powerlaw(30_000, seed=99), 64, 1)
@@ -120,3 +133,32 @@ def test_batch_graph_replays_with_eager_work_between():
             sellcs.sell_spmv(hh, xx, yy)
         sellcs.sell_spmv(other, xo, yo)
         torch.cuda.synchronize()
+
+
+def test_batch_autotune_picks_model_sigmas_and_a_working_C():
+    """The batch autotuner gives every matrix the sigma whose layout has the
+    fewest model bytes (checked against the oracle's layouts) and returns a C
+    whose batch matches the oracle."""
+    import torch
+    from paper_1307_6209_amd import sellcs
+    from gpu_util import dev_crs
+    mats = make_batch(8, 11, 1000, 30000)
+    dev = [dev_crs(A) for A in mats]
+    Cs, sigmas = (16, 32), (1, 256, 1 << 40)
+    r = sellcs.sell_batch_autotune([(rp, cc, vv, A.ncols) for (rp, cc, vv), A in zip(dev, mats)], C=Cs,
+                                   sigma=sigmas, reps=5)
+    say("batch autotune", r)
+    assert r["C"] in Cs and r["candidates"] == len(Cs) and r["gflops"] > 0
+    for A, sg in zip(mats, r["sigmas"]):
+        def model_bytes(s):
+            L = oracle.sell_build(A, r["C"], s)
+            return 12.0 * L["padded"] + (4.0 * A.nrows if min(s, A.nrows) > 1 else 0.0)
+        best = min(sigmas, key=lambda s: (model_bytes(s), sigmas.index(s)))
+        assert model_bytes(sg) == model_bytes(best)
+    hs = [sellcs.sell_build(rp, cc, vv, A.ncols, r["C"], sg) for (rp, cc, vv), A, sg in zip(dev, mats, r["sigmas"])]
+    b = sellcs.sell_batch_create(hs)
+    xs = [synth.uniform(A.ncols, 120 + i, 1) for i, A in enumerate(mats)]
+    ys = run(b, mats, xs, (torch.float64, torch.float64))
+    for A, x, y in zip(mats, xs, ys):
+        check_fp64(A, y, x)
+    b.close()
