@@ -133,6 +133,13 @@ def graph_time(fn, launches: int, replays: int = 5) -> float:
     return e0.elapsed_time(e1) * 1e-3 / (replays * launches)
 
 
+def normwise(y, yref) -> float:
+    """||y - yref||_2 / ||yref||_2 of two device vectors (in float64)."""
+    import torch
+    d = torch.linalg.vector_norm(y.double() - yref)
+    return float(d / torch.clamp(torch.linalg.vector_norm(yref), min=1e-300))
+
+
 def cold_time(fn, flush, reps: int = 21) -> float:
     """Median seconds of single calls of fn, each timed by its own events
     right after a read-modify-write of `flush` (1 GiB: evicts every L2 and
@@ -238,13 +245,20 @@ def run_forms(args, probes) -> dict:
                                       "frac_of_gather_probe": round(8.0 * A.nnz / t * 1e-9 / probes["gather_16mib_gbs"],
                                                                     4)}
         h.close()
-    # reduced-precision storage at the globally sorted layout
+    # reduced-precision storage at the globally sorted layout; normwise error
+    # against the FP64 product of the same rounded x
     xf = x.float()
+    h = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows)
+    y64 = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    sellcs.sell_spmv(h, xf.double(), y64)
+    h.close()
     for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
         h = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, val_dtype=vd, acc_dtype=ad)
         yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
         t = time_calls(lambda: sellcs.sell_spmv(h, xf, yf), max(20, args.steps // 5), 5)
-        pl["C32_sigma%d_%s_val_%s_acc" % (A.nrows, vd, ad)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2)}
+        pl["C32_sigma%d_%s_val_%s_acc" % (A.nrows, vd, ad)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2),
+                                                               "normwise_err_vs_fp64": float(
+                                                                   "%.3g" % normwise(yf, y64))}
         h.close()
     hs_ = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, permute_columns=True)
     xp = torch.empty_like(x)
@@ -423,17 +437,23 @@ def main():
         "probes": probes,
         "kernel_source_hash": src_hash,
     }
-    # precision forms on the same matrix, at the headline C and at C = 64
-    forms = {}
+    # precision forms on the same matrix, at the headline C and at C = 64, with
+    # the normwise error against the FP64 product of the same rounded x
+    forms, errs = {}, {}
+    xf = x.float()
+    y64 = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    sellcs.sell_spmv(h, xf.double(), y64)
     for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
         for C in sorted({HEADLINE["C"], 64}):
             hf = sellcs.sell_build(r, c, v, A.ncols, C, HEADLINE["sigma"], val_dtype=vd, acc_dtype=ad)
-            xf = x.float()
             yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
             t = time_calls(lambda: sellcs.sell_spmv(hf, xf, yf), max(50, args.steps // 4), 10)
-            forms["%s_val_%s_acc_C%d" % (vd, ad, C)] = round(2.0 * A.nnz / t * 1e-9, 2)
+            key = "%s_val_%s_acc_C%d" % (vd, ad, C)
+            forms[key] = round(2.0 * A.nnz / t * 1e-9, 2)
+            errs[key] = float("%.3g" % normwise(yf, y64))
             hf.close()
     line["forms_stencil27_160_gfs"] = forms
+    line["forms_stencil27_160_normwise_err_vs_fp64"] = errs
     # the paper's comparison on one device: CRS (one lane per row, and L lanes
     # per row with a cross-lane reduction) against SELL-C-sigma
     crs = {}
