@@ -303,9 +303,13 @@ def model_report(model, b_read, gfs, achieved, inf, A, sizes, traffic) -> dict:
            "balance_ideal_alpha_bytes_per_flop": round(bal, 4), "P_model_gfs": round(p_model, 1),
            "frac_of_model": round(gfs / p_model, 4), "P_bar_paper_gfs": round(model.best_attainable(b_read, inf["beta"]), 1)}
     if traffic:
-        rep["alpha_measured"] = round(model.general_alpha_from_volume(traffic, A.nnz, inf["beta"], nnzr, inf["C"], 1,
-                                                                      sizes), 5)
+        alpha = model.general_alpha_from_volume(traffic, A.nnz, inf["beta"], nnzr, inf["C"], 1, sizes)
+        bal_m = model.general_balance(alpha, inf["beta"], nnzr, inf["C"], 1, sizes)
+        rep["alpha_measured"] = round(alpha, 5)
         rep["alpha_ideal"] = round(1.0 / nnzr, 5)
+        # the model's bound with the measured right-hand-side traffic
+        rep["P_model_alpha_measured_gfs"] = round(b_read / bal_m, 1)
+        rep["frac_of_model_alpha_measured"] = round(gfs / (b_read / bal_m), 4)
     return rep
 
 
@@ -463,8 +467,9 @@ def main():
         crs["crs_L%d" % L] = round(2.0 * A.nnz / t * 1e-9, 2)
     crs["sell_%d_%d" % (HEADLINE["C"], HEADLINE["sigma"])] = round(gfs, 2)
     line["crs_vs_sell_stencil27_160_gfs"] = crs
-    # SELL-32-1 against the autotuned SELL-C-sigma on the same matrix
-    tuned = sellcs.sell_autotune(r, c, v, A.ncols, k=1, C=(32, 64), sigma=(1, 1024, 131072), unroll=(4, 8), reps=20)
+    # SELL-32-1 against SELL-32-sigma autotuned over sigma = 2^0 .. 2^17 and n
+    sig_space = tuple(1 << i for i in range(18)) + (A.nrows,)
+    tuned = sellcs.sell_autotune(r, c, v, A.ncols, k=1, C=(32,), sigma=sig_space, unroll=(4, 8), reps=20)
     line["autotuned_stencil27_160"] = {key: (round(val, 3) if isinstance(val, float) else val)
                                        for key, val in tuned.items()}
     h.close()
