@@ -90,7 +90,7 @@ def cpu_baseline(A, x, budget_s: float = 10.0, C: int = 32, sigma: int = 1) -> d
         t0 = time.perf_counter()
         oracle.crs_spmv(A, x, nthreads=nthreads, sched=sched)
         t1 = time.perf_counter() - t0
-        reps = int(max(3, min(500, budget / max(t1, 1e-6))))
+        reps = int(max(3, min(20000, budget / max(t1, 1e-6))))
         t0 = time.perf_counter()
         for _ in range(reps):
             oracle.crs_spmv(A, x, nthreads=nthreads, sched=sched)
