@@ -64,19 +64,24 @@ def to_dev(A):
     return (torch.from_numpy(A.rpt).cuda(), torch.from_numpy(A.col).cuda(), torch.from_numpy(A.val).cuda())
 
 
-def time_calls(fn, steps: int, warmup: int):
-    """Average seconds per call of fn over `steps` calls after `warmup`."""
+def time_calls(fn, steps: int, warmup: int, repeats: int = 5):
+    """Seconds per call of fn after `warmup` calls: `steps` back-to-back calls
+    cut into `repeats` groups, each timed by its own events; the median group
+    average (repeats = 1: the average over exactly `steps` calls)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
+    per = max(1, steps // repeats) if repeats > 1 else steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(repeats)]
+    for e0, e1 in evs:
+        e0.record()
+        for _ in range(per):
+            fn()
+        e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e-3 / steps
+    ts = sorted(e0.elapsed_time(e1) * 1e-3 / per for e0, e1 in evs)
+    return ts[len(ts) // 2]
 
 
 def cpu_baseline(A, x, budget_s: float = 10.0, C: int = 32, sigma: int = 1) -> dict:
@@ -409,7 +414,7 @@ def main():
               "gather_16mib_gbs": round(sellcs.sell_probe_bandwidth(2, 16 << 20, 5), 1),
               "gather_2gib_gbs": round(sellcs.sell_probe_bandwidth(2, 2 << 30, 5), 1)}
 
-    sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup)
+    sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup, repeats=1)
     gfs = 2.0 * A.nnz / sec * 1e-9
     sizes = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1)
     alg = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes)

@@ -216,8 +216,13 @@ sell_status sell_batch_create_persistent(const sell_handle *hs, int32_t count,
 /*
  * sell_batch_spmv -- ys[b] = A_b xs[b] for every matrix of the batch, as one
  * graph launch on stream (asynchronous). xs and ys are host arrays of count
- * device pointers. When they differ from the previous call, the device copy
- * of the pointer table is rewritten first (this synchronises the stream).
+ * device pointers (x and y dtypes of the handles; each ys[b] fully
+ * overwritten, no xs[b] may overlap a ys[c]). When they differ from the
+ * previous call, the device copy of the pointer table is rewritten first,
+ * after a device-wide synchronisation (earlier launches of the batch may
+ * still read it); with unchanged pointers the call only launches the graph.
+ * Calls on one batch must not overlap in time (they share the pointer table
+ * and the partial-sum buffer of split chunks).
  */
 sell_status sell_batch_spmv(sell_batch b, const void *const *xs,
                             void *const *ys, void *stream);

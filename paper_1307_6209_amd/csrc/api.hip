@@ -734,7 +734,8 @@ extern "C" sell_status sell_batch_spmv(sell_batch b, const void *const *xs, void
     if (b->host_mats[i].x != xs[i] || b->host_mats[i].y != ys[i]) changed = true;
   }
   if (changed) {
-    SELL_HIP(hipStreamSynchronize(s));
+    // earlier launches of this batch, on any stream, may still read the table
+    SELL_HIP(hipDeviceSynchronize());
     for (size_t i = 0; i < b->hs.size(); ++i) {
       b->host_mats[i].x = xs[i];
       b->host_mats[i].y = ys[i];
