@@ -292,18 +292,17 @@ def sell_info(h: SellMatrix) -> dict:
     return {name: getattr(info, name) for name, _ in SellInfo._fields_}
 
 
-def sell_export(h: SellMatrix) -> dict:
-    """Host copies (numpy) of perm, cl, cs, col and val (bf16 as uint16 bits)."""
+def sell_export(h: SellMatrix, parts=("perm", "cl", "cs", "col", "val")) -> dict:
+    """Host copies (numpy) of perm, cl, cs, col and val (bf16 as uint16 bits);
+    only the arrays named in parts are copied."""
     inf = h.info
-    perm = np.empty(inf["nrows"], np.int32)
-    cl = np.empty(inf["nchunks"], np.int32)
-    cs = np.empty(inf["nchunks"] + 1, np.int64)
-    col = np.empty(inf["padded"], np.int32)
     vdt = {0: np.float64, 1: np.float32, 2: np.uint16}[inf["val_dtype"]]
-    val = np.empty(inf["padded"], vdt)
-    p = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
-    _check(lib().sell_export(h.handle, p(perm), p(cl), p(cs), p(col), p(val)), "sell_export")
-    return dict(perm=perm, cl=cl, cs=cs, col=col, val=val)
+    shapes = {"perm": (inf["nrows"], np.int32), "cl": (inf["nchunks"], np.int32), "cs": (inf["nchunks"] + 1, np.int64),
+              "col": (inf["padded"], np.int32), "val": (inf["padded"], vdt)}
+    out = {k: np.empty(shapes[k][0], shapes[k][1]) for k in parts}
+    p = lambda k: ctypes.c_void_p(out[k].ctypes.data) if k in out else None  # noqa: E731
+    _check(lib().sell_export(h.handle, p("perm"), p("cl"), p("cs"), p("col"), p("val")), "sell_export")
+    return out
 
 
 def sell_permute(h: SellMatrix, x, xp, stream=None):
