@@ -416,7 +416,8 @@ def main():
 
     sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup, repeats=1)
     gfs = 2.0 * A.nnz / sec * 1e-9
-    sizes = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1)
+    sizes = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1, xwindow=inf["xwindow"] == 1,
+                            segments_per_chunk=inf["xsegments"] / max(1, inf["nchunks"]))
     alg = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes)
     achieved = alg / sec * 1e-9
     src_hash = kernel_source_hash()
@@ -437,7 +438,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "stencil27_160 (27-point stencil, 160^3 grid)", "n": A.nrows, "nnz": A.nnz,
                    "format": "SELL-%d-%d" % (HEADLINE["C"], HEADLINE["sigma"]), "beta": round(inf["beta"], 6),
-                   "padded_slots": inf["padded"], "index": "int32", "values": "f64", "x": "f64", "y": "f64"},
+                   "padded_slots": inf["padded"],
+                   "index": "uint16 window positions (x window staged in LDS)" if inf["xwindow"] else "int32",
+                   "values": "f64", "x": "f64", "y": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg},
@@ -471,6 +474,12 @@ def main():
                        10)
         crs["crs_L%d" % L] = round(2.0 * A.nnz / t * 1e-9, 2)
     crs["sell_%d_%d" % (HEADLINE["C"], HEADLINE["sigma"])] = round(gfs, 2)
+    # the same layout multiplied with the global column indices (x gathered
+    # through L2) instead of the x window in LDS
+    hg = sellcs.sell_build(r, c, v, A.ncols, HEADLINE["C"], HEADLINE["sigma"], xwindow=-1)
+    t = time_calls(lambda: sellcs.sell_spmv(hg, x, y), max(50, args.steps // 4), 10)
+    crs["sell_%d_%d_global_index" % (HEADLINE["C"], HEADLINE["sigma"])] = round(2.0 * A.nnz / t * 1e-9, 2)
+    hg.close()
     line["crs_vs_sell_stencil27_160_gfs"] = crs
     # SELL-32-1 against SELL-32-sigma autotuned over sigma = 2^0 .. 2^17 and n
     sig_space = tuple(1 << i for i in range(18)) + (A.nrows,)

@@ -88,6 +88,18 @@ typedef struct {
                            P A P^T and x, y live in sorted order -- the form the
                            paper recommends for iterative solvers (Sect. 3.4);
                            see sell_permute / sell_unpermute */
+  int32_t xwindow;      /* x window in LDS for sell_spmv: the distinct columns of
+                           each group of 4 chunks (one workgroup) are staged in
+                           LDS once and the slots also store their 16-bit
+                           position in it (2 bytes streamed instead of 4, x read
+                           from LDS; same result bit for bit). 0: used when it
+                           fits (C in 8..64, vec 1 or 2, no split chunks, at most
+                           8192 slots and 1024 runs of consecutive columns per
+                           group, window <= 16 KiB); -1: never;
+                           1: required (SELL_ERR_UNSUPPORTED when it cannot be
+                           built, window up to 64 KiB). The global column
+                           indices are kept for sell_export, sell_spmmv and the
+                           batch. */
   const sell_allocator *alloc; /* NULL: hipMalloc/hipFree */
 } sell_build_opts;
 
@@ -110,6 +122,9 @@ typedef struct {
   int32_t has_perm;      /* 0 when the row order is the identity (sigma == 1) */
   int32_t permuted_columns; /* 1 when built with permute_columns */
   int64_t device_bytes;  /* device memory held by the handle */
+  int32_t xwindow;       /* 1 when sell_spmv stages x windows in LDS */
+  int32_t xwindow_max;   /* largest window, in x elements */
+  int64_t xsegments;     /* runs of consecutive columns over all windows */
 } sell_info_t;
 
 /*

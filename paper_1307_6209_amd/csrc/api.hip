@@ -213,6 +213,7 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
     return fail(SELL_ERR_UNSUPPORTED, "sell_build: permute_columns needs a square matrix");
   if (o.alloc && (!o.alloc->alloc || !o.alloc->free))
     return fail(SELL_ERR_INVALID_ARG, "sell_build: allocator needs alloc and free");
+  if (o.xwindow < -1 || o.xwindow > 1) return fail(SELL_ERR_INVALID_ARG, "sell_build: xwindow must be -1, 0 or 1");
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::unique_ptr<sell_matrix> h(new sell_matrix());
@@ -374,6 +375,57 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
   } else {
     h->nunits = h->nitems;
   }
+
+  // x windows for LDS staging: when they fit (xwindow 0) or required (1)
+  if (o.xwindow >= 0) {
+    const int V = g.V;
+    const bool shape_ok = C >= 8 && C <= 64 && (V == 1 || V == 2) && !h->units && h->padded > 0;
+    if (!shape_ok) {
+      if (o.xwindow == 1)
+        return fail(SELL_ERR_UNSUPPORTED, "sell_build: the x window needs C in 8..64, vec 1 or 2 and no split chunks");
+    } else {
+      const int64_t ngroups = (nc + sell::kXwChunks - 1) / sell::kXwChunks;
+      struct XwSmall {
+        uint32_t flags;
+        int32_t maxwin;
+        int32_t maxseg;
+        int32_t pad;
+        int64_t nseg;
+      };
+      XwSmall *dxs = static_cast<XwSmall *>(tmp.get(sizeof(XwSmall)));
+      int64_t *cnt = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)(ngroups + 1)));
+      int64_t *offs = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)(ngroups + 1)));
+      int64_t *stmp = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)sell::scan_tmp_elems(ngroups + 1)));
+      if (!dxs || !cnt || !offs || !stmp) return fail(SELL_ERR_OOM, "sell_build: x window temporaries");
+      SELL_HIP(hipMemsetAsync(dxs, 0, sizeof(XwSmall), s));
+      SELL_HIP(sell::build_xw_count(h->col, h->cs, nc, cnt, &dxs->flags, &dxs->maxwin, &dxs->maxseg, s));
+      SELL_HIP(sell::build_scan(cnt, offs, ngroups + 1, stmp, s));
+      SELL_HIP(hipMemcpyAsync(&dxs->nseg, offs + ngroups, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+      XwSmall xs{};
+      SELL_HIP(hipMemcpyAsync(&xs, dxs, sizeof(XwSmall), hipMemcpyDeviceToHost, s));
+      SELL_HIP(hipStreamSynchronize(s));
+      const size_t xsz = h->xdt == SELL_F64 ? 8 : 4;
+      const size_t budget = o.xwindow == 1 ? (size_t)64 << 10 : (size_t)16 << 10;
+      if (xs.flags || (size_t)xs.maxwin * xsz > budget || xs.maxseg > sell::kXwMaxSeg) {
+        if (o.xwindow == 1)
+          return fail(SELL_ERR_UNSUPPORTED,
+                      "sell_build: x window too large (more than 8192 slots or 1024 column runs per group, or "
+                      "window over 64 KiB)");
+      } else {
+        h->xsegoff = static_cast<int64_t *>(owned_alloc(h.get(), mem, sizeof(int64_t) * (size_t)(ngroups + 1)));
+        h->xseg = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * 3 * (size_t)xs.nseg));
+        h->lcol = static_cast<uint16_t *>(owned_alloc(h.get(), mem, sizeof(uint16_t) * (size_t)h->padded));
+        if (!h->xsegoff || !h->xseg || !h->lcol) return fail(SELL_ERR_OOM, "sell_build: x window arrays");
+        SELL_HIP(hipMemcpyAsync(h->xsegoff, offs, sizeof(int64_t) * (size_t)(ngroups + 1), hipMemcpyDeviceToDevice,
+                                s));
+        SELL_HIP(sell::build_xw_fill(h->col, h->cs, nc, h->xsegoff, h->xseg, h->lcol, s));
+        SELL_HIP(hipStreamSynchronize(s));
+        h->nxseg = xs.nseg;
+        h->xwin_max = xs.maxwin;
+        h->xseg_max = xs.maxseg;
+      }
+    }
+  }
   guard.armed = false;
   *out = h.release();
   return SELL_OK;
@@ -422,8 +474,15 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   // padding-heavy layouts skip the gathers of their zero slots; near-dense
   // chunks skip the per-slot test
   const bool skip_zero = h->beta < 0.9;
-  hipError_t e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a,
-                                   static_cast<hipStream_t>(stream));
+  hipError_t e;
+  if (h->lcol) {  // x windows staged in LDS
+    const sell::XwArgs w{h->lcol, h->xsegoff, h->xseg, h->xwin_max};
+    const size_t lds = (((size_t)h->xwin_max * (h->xdt == SELL_F64 ? 8 : 4) + 7) & ~(size_t)7) +
+                       8 * (size_t)h->xseg_max;
+    e = sell::launch_spmv_xw(h->combo, h->C, h->g.V, a, w, lds, static_cast<hipStream_t>(stream));
+  } else {
+    e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a, static_cast<hipStream_t>(stream));
+  }
   if (e != hipSuccess) return hip_fail("sell_spmv launch", e);
   return SELL_OK;
 }
@@ -498,6 +557,9 @@ extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
   r.has_perm = h->perm ? 1 : 0;
   r.permuted_columns = h->sym ? 1 : 0;
   r.device_bytes = h->device_bytes;
+  r.xwindow = h->lcol ? 1 : 0;
+  r.xwindow_max = h->xwin_max;
+  r.xsegments = h->nxseg;
   *info = r;
   return SELL_OK;
 }

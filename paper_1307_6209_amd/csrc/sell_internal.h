@@ -122,6 +122,19 @@ struct BatchArgs {
   int32_t seg_cols;
 };
 
+// x window of a product workgroup (LDS staging): groups of kXwChunks
+// consecutive chunks, at most kXwMaxSlots slots each.
+constexpr int kXwChunks = 4;
+constexpr int kXwMaxSlots = 8192;
+struct XwArgs {
+  const uint16_t *lcol;   // window position of every slot
+  const int64_t *segoff;  // ngroups + 1 segment offsets
+  const int32_t *seg;     // per segment: start column, window position, length
+  int32_t wcap;           // LDS elements reserved for the window (the largest one)
+};
+// Most segments a group's window may have (its table is staged in LDS too).
+constexpr int kXwMaxSeg = 1024;
+
 enum DtypeCombo {
   COMBO_F64_F64 = 0,   // val f64, x f64, acc f64
   COMBO_F32_F32 = 1,   // val f32, x f32, acc f32
@@ -136,6 +149,11 @@ enum DtypeCombo {
 // skip_zero: slots holding value 0 skip their gather (for padding-heavy layouts).
 hipError_t launch_spmv(int combo, int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
+// Product with the x window staged in LDS (C in 8..64, V 1 or 2, no split
+// chunks); lds_bytes: the largest window times the x element size, rounded
+// up to 8 bytes, plus 8 bytes per segment of the largest segment table.
+hipError_t launch_spmv_xw(int combo, int C, int V, const SpmvArgs &a, const XwArgs &w, size_t lds_bytes,
+                          hipStream_t s);
 hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, hipStream_t s);
 // Resident waves per CU of the batched kernel (persistent grid size).
 int batch_waves_per_cu(int combo, int C, int U);
@@ -158,6 +176,14 @@ hipError_t build_fill(const int64_t *rpt, const int32_t *col, const double *val,
                       int64_t padded, const int32_t *cmap, int32_t *scol, void *sval, int val_dtype,
                       hipStream_t s);
 hipError_t build_invert(const int32_t *perm, int64_t n, int32_t *iperm, hipStream_t s);
+// x windows: segment count per group (nseg: ngroups + 1 int64, the last set
+// to 0), the largest window (*maxwin, zeroed by the caller), flag bit 1 when
+// a group holds more than kXwMaxSlots slots; then the segments and the
+// window position of every slot.
+hipError_t build_xw_count(const int32_t *col, const int64_t *cs, int64_t nchunks, int64_t *nseg, uint32_t *flags,
+                          int32_t *maxwin, int32_t *maxseg, hipStream_t s);
+hipError_t build_xw_fill(const int32_t *col, const int64_t *cs, int64_t nchunks, const int64_t *segoff, int32_t *seg,
+                         uint16_t *lcol, hipStream_t s);
 // out[p] = in[perm[p]] (scatter = false) or out[perm[p]] = in[p] (scatter = true).
 hipError_t permute_vector(const void *in, void *out, const int32_t *perm, int64_t n, int elem_bytes, bool scatter,
                           hipStream_t s);
@@ -204,6 +230,13 @@ struct sell_matrix {
   int64_t nsegs = 0;                  // total segments of split items
   sell::SplitDesc *splits = nullptr;  // per split id
   void *partial = nullptr;            // nsegs * rpw * next_pow2(kmax) doubles
+
+  uint16_t *lcol = nullptr;     // x window mode: window position of every slot
+  int64_t *xsegoff = nullptr;   // ngroups + 1 segment offsets
+  int32_t *xseg = nullptr;      // per segment: start column, window position, length
+  int64_t nxseg = 0;
+  int32_t xwin_max = 0;         // largest window, in x elements
+  int32_t xseg_max = 0;         // most segments of one window
 
   std::vector<int32_t> h_cl;    // host copy of the chunk widths (batch planning)
 

@@ -226,6 +226,143 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
   for (int v = 0; v < VV; ++v) part[v] = acc[v];
 }
 
+// Product with the x window in LDS. Workgroup g (kXwChunks waves, one chunk
+// each) first issues its first U wave steps of val and of the 16-bit window
+// positions, then stages its window -- every element with one load, its
+// segment found by binary search -- and after the barrier runs the steps of
+// spmv_unit (same lanes, same order of the multiply-adds, same cross-lane
+// sum: the result equals the global-index product bit for bit) with x read
+// from LDS.
+template <int COMBO, int C, int VV, int U>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv_xw(SpmvArgs a, XwArgs xa) {
+  using V = typename Types<COMBO>::V;
+  using X = typename Types<COMBO>::X;
+  using A = typename Types<COMBO>::A;
+  static_assert(kXwChunks == kWavesPerBlock, "one chunk per wave");
+  static_assert(C <= 64 && C % VV == 0, "one wave covers a chunk");
+  constexpr int T = 64 * VV / C;           // chunk columns per wave step
+  constexpr int LPC = C / VV;              // lanes covering one chunk column
+  constexpr int64_t STRIDE = (int64_t)T * C;
+  extern __shared__ unsigned char xw_lds[];
+  X *xw = reinterpret_cast<X *>(xw_lds);
+
+  const int64_t g = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t chunk = g * kXwChunks + (threadIdx.x >> 6);
+  const bool live = chunk < a.nwork;
+  const int64_t base = live ? a.cs[chunk] : 0;
+  const int cl = live ? a.cl[chunk] : 0;
+  const int rl0 = (VV * lane) % C, t = (VV * lane) / C;
+  const int64_t off0 = base + (int64_t)t * C + rl0;
+  const uint16_t *cp = xa.lcol + off0;
+  const V *vp = static_cast<const V *>(a.val) + off0;
+  const int full = cl / T, se = (cl + T - 1) / T;
+
+  uint16_t ci[U][VV];
+  V raw[U][VV];
+  const bool first = U <= full;
+  if (first) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ld_stream<VV>(cp + (int64_t)u * STRIDE, ci[u]);
+      ld_stream<VV>(vp + (int64_t)u * STRIDE, raw[u]);
+    }
+  }
+  // stage the window: first the group's segment table (start column,
+  // window position) into LDS behind the window, then every window element
+  // with one load, its segment found by binary search in LDS
+  {
+    const X *x = static_cast<const X *>(a.x);
+    int2 *segt = reinterpret_cast<int2 *>(xw_lds + (((size_t)xa.wcap * sizeof(X) + 7) & ~(size_t)7));
+    const int64_t s0 = xa.segoff[g];
+    const int ns = (int)(xa.segoff[g + 1] - s0);
+    for (int k = threadIdx.x; k < ns; k += 64 * kWavesPerBlock)
+      segt[k] = make_int2(xa.seg[3 * (s0 + k)], xa.seg[3 * (s0 + k) + 1]);
+    const int nwin = ns > 0 ? xa.seg[3 * (s0 + ns - 1) + 1] + xa.seg[3 * (s0 + ns - 1) + 2] : 0;
+    __syncthreads();
+    constexpr int K = 8;
+    for (int b = 0; b < nwin; b += 64 * kWavesPerBlock * K) {
+      X tmp[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = b + k * 64 * kWavesPerBlock + (int)threadIdx.x;
+        tmp[k] = (X)0;
+        if (i < nwin) {
+          int lo = 0, hi = ns - 1;  // last segment with position <= i
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segt[mid].y <= i) lo = mid;
+            else hi = mid - 1;
+          }
+          tmp[k] = x[segt[lo].x + (i - segt[lo].y)];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = b + k * 64 * kWavesPerBlock + (int)threadIdx.x;
+        if (i < nwin) xw[i] = tmp[k];
+      }
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+
+  A acc[VV];
+#pragma unroll
+  for (int v = 0; v < VV; ++v) acc[v] = 0;
+  int s = 0;
+  if (first) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xw[ci[u][v]], acc[v]);
+    s = U;
+  }
+  for (; s + U <= full; s += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
+      ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xw[ci[u][v]], acc[v]);
+  }
+  for (; s < se; ++s) {  // the last steps; the very last may be partial
+    if (s * T + t < cl) {
+      uint16_t c1[VV];
+      V r1[VV];
+      ld_stream<VV>(cp + (int64_t)s * STRIDE, c1);
+      ld_stream<VV>(vp + (int64_t)s * STRIDE, r1);
+#pragma unroll
+      for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(r1[v]), xw[c1[v]], acc[v]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= LPC; off >>= 1)
+#pragma unroll
+    for (int v = 0; v < VV; ++v) acc[v] += __shfl_xor(acc[v], off);
+  if (t != 0) return;
+  A *y = static_cast<A *>(a.y);
+  const int64_t p0 = chunk * C + rl0;
+  if constexpr (VV > 1) {
+    if (!a.perm && p0 + VV <= a.nrows && (reinterpret_cast<uintptr_t>(y + p0) & (VV * sizeof(A) - 1)) == 0) {
+      typedef A avt __attribute__((ext_vector_type(VV)));
+      avt o;
+#pragma unroll
+      for (int v = 0; v < VV; ++v) o[v] = acc[v];
+      __builtin_nontemporal_store(o, reinterpret_cast<avt *>(y + p0));
+      return;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < VV; ++v) {
+    const int64_t p = p0 + v;
+    if (p < a.nrows) __builtin_nontemporal_store(acc[v], y + (a.perm ? (int64_t)a.perm[p] : p));
+  }
+}
+
 // Adds the segment sums of split row slices in segment order and writes y.
 // One wave per split slice.
 template <int COMBO, int C>
@@ -504,6 +641,22 @@ hipError_t launch_spmv_zs(int C, int U, int VV, const SpmvArgs &a, hipStream_t s
 template <int COMBO>
 hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a, hipStream_t s) {
   return skip_zero ? launch_spmv_zs<COMBO, true>(C, U, VV, a, s) : launch_spmv_zs<COMBO, false>(C, U, VV, a, s);
+}
+
+// C in {8, 16, 32, 64}; V = 1 with 4 steps in flight, V = 2 with 2.
+template <int COMBO>
+hipError_t launch_spmv_xw_t(int C, int VV, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
+  if (a.nwork <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((a.nwork + kXwChunks - 1) / kXwChunks);
+#define SELL_L(CC, VVV, UU)                                                                                    \
+  if (C == CC && VV == VVV) {                                                                                  \
+    hipLaunchKernelGGL((k_spmv_xw<COMBO, CC, VVV, UU>), dim3(nb), dim3(64 * kWavesPerBlock), lds, s, a, w);   \
+    return hipGetLastError();                                                                                  \
+  }
+  SELL_L(8, 1, 4) SELL_L(16, 1, 4) SELL_L(32, 1, 4) SELL_L(64, 1, 4)
+  SELL_L(8, 2, 2) SELL_L(16, 2, 2) SELL_L(32, 2, 2) SELL_L(64, 2, 2)
+#undef SELL_L
+  return hipErrorInvalidValue;
 }
 
 template <int COMBO>

@@ -59,7 +59,7 @@ class Sizes:
     sx: int = 8   # x element
     sy: int = 8   # y element traffic per row (8: written once; 16: read and written)
     sp: int = 0   # permutation bytes per row (4 when sigma > 1)
-    meta: int = 12  # cl (4) + cs (8) per chunk
+    meta: float = 12  # cl (4) + cs (8) per chunk (+ window tables with the x window)
 
 
 def general_balance(alpha: float, beta: float, nnzr: float, C: int, k: int = 1, s: Sizes = Sizes()) -> float:
@@ -84,8 +84,15 @@ def algorithmic_bytes(nrows: int, ncols: int, padded: int, nchunks: int, k: int 
     return int((s.sv + s.si) * padded + s.sx * ncols * k + s.sy * nrows * k + s.sp * nrows + s.meta * nchunks)
 
 
-def sizes_for(val_dtype: str, acc_dtype: str, sigma_gt_1: bool) -> Sizes:
+def sizes_for(val_dtype: str, acc_dtype: str, sigma_gt_1: bool, xwindow: bool = False,
+              segments_per_chunk: float = 0.0) -> Sizes:
+    """Element sizes of a product. With the x window staged in LDS the
+    streamed index is the 2-byte window position, and each chunk also moves
+    its share of the window tables: 2 bytes of group offsets (8 bytes per
+    group of 4 chunks) and 12 bytes per segment."""
     sv = {"f64": 8, "f32": 4, "bf16": 2}[val_dtype]
     sx = 8 if val_dtype == "f64" else 4
     sy = 8 if acc_dtype == "f64" else 4
+    if xwindow:
+        return Sizes(sv=sv, si=2, sx=sx, sy=sy, sp=4 if sigma_gt_1 else 0, meta=12 + 2 + 12 * segments_per_chunk)
     return Sizes(sv=sv, si=4, sx=sx, sy=sy, sp=4 if sigma_gt_1 else 0)

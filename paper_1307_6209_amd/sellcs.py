@@ -42,7 +42,7 @@ class SellAllocator(ctypes.Structure):
 class SellBuildOpts(ctypes.Structure):
     _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("vec", c_i32),
                 ("seg_cols", c_i32), ("ktile", c_i32), ("kmax", c_i32), ("permute_columns", c_i32),
-                ("alloc", ctypes.POINTER(SellAllocator))]
+                ("xwindow", c_i32), ("alloc", ctypes.POINTER(SellAllocator))]
 
 
 class SellInfo(ctypes.Structure):
@@ -50,7 +50,8 @@ class SellInfo(ctypes.Structure):
                 ("nchunks", c_i64), ("padded", c_i64), ("beta", c_d), ("zeta", c_d), ("max_row_len", c_i64),
                 ("val_dtype", ctypes.c_int), ("x_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int),
                 ("lanes_per_row", c_i32), ("unroll", c_i32), ("vec", c_i32), ("seg_cols", c_i32), ("nunits", c_i64),
-                ("nsplit", c_i64), ("has_perm", c_i32), ("permuted_columns", c_i32), ("device_bytes", c_i64)]
+                ("nsplit", c_i64), ("has_perm", c_i32), ("permuted_columns", c_i32), ("device_bytes", c_i64),
+                ("xwindow", c_i32), ("xwindow_max", c_i32), ("xsegments", c_i64)]
 
 
 class SellTuneSpace(ctypes.Structure):
@@ -246,9 +247,10 @@ class SellMatrix:
 
 def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
                unroll: int = 0, vec: int = 0, seg_cols: int = 0, ktile: int = 0, kmax: int = 0,
-               permute_columns: bool = False, allocator: TorchAllocator | None = None,
+               permute_columns: bool = False, xwindow: int = 0, allocator: TorchAllocator | None = None,
                stream=None) -> SellMatrix:
     """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64).
+    xwindow: 0 stage x windows in LDS when they fit, -1 never, 1 required.
     allocator: a TorchAllocator to take the handle's device memory from
     torch's caching allocator (default: the library's hipMalloc)."""
     import torch
@@ -259,7 +261,8 @@ def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "
     if acc_dtype is None:
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
     o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax,
-                      1 if permute_columns else 0, ctypes.pointer(allocator.struct) if allocator else None)
+                      1 if permute_columns else 0, xwindow,
+                      ctypes.pointer(allocator.struct) if allocator else None)
     h = c_p()
     _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
     return SellMatrix(h, allocator)

@@ -77,6 +77,10 @@ def test_host_side_argument_errors(L):
         badv = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, vec=vec)
         assert L.sell_build(ctypes.byref(A), C, 1, ctypes.byref(badv), None,
                             ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    for xw in (-2, 2):
+        badx = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, xwindow=xw)
+        assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badx), None,
+                            ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmv(None, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmmv(None, None, None, 4, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_batch_create(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG

@@ -1,0 +1,123 @@
+"""The x window staged in LDS (xwindow build option): the product equals the
+global-index product bit for bit (same lanes, same order of the multiply-adds;
+padding reads x[0] through the window as it does directly), stays within the
+oracle's bound, leaves the exported layout unchanged, falls back silently
+when a window does not fit, and is refused with an error when required but
+impossible."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_layout_equal, build, check_fp64, say, spmv_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def banded(n, seed, half=40, max_len=30):
+    """Random rows whose columns lie within +-half of the diagonal."""
+    A = synth.random_crs(n, n, seed=seed, max_len=max_len, empty_frac=0.15)
+    lens = np.diff(A.rpt)
+    rows = np.repeat(np.arange(n), lens)
+    col = np.clip(rows + (A.col.astype(np.int64) % (2 * half + 1)) - half, 0, n - 1)
+    # keep each row's columns sorted and distinct enough for a CRS
+    out = []
+    for i in range(n):
+        c = np.unique(col[A.rpt[i]:A.rpt[i + 1]])
+        out.append(c)
+    rpt = np.zeros(n + 1, np.int64)
+    np.cumsum([len(c) for c in out], out=rpt[1:])
+    cc = np.concatenate(out).astype(np.int32) if rpt[-1] else np.zeros(0, np.int32)
+    val = synth.uniform(int(rpt[-1]), seed, 3)
+    return synth.CRS(n, n, rpt, cc, val)
+
+
+MATS = [
+    ("stencil27_24", lambda: synth.stencil27(24)),
+    ("lap5_96", lambda: synth.lap5(96)),
+    ("banded_3000", lambda: banded(3000, 7)),
+]
+
+
+@pytest.mark.parametrize("name,make", MATS, ids=[m[0] for m in MATS])
+@pytest.mark.parametrize("C,sigma,vec", [(32, 1, 0), (32, 1, 1), (8, 1, 2), (16, 64, 0), (64, 1, 0), (64, 4096, 1),
+                                         (32, 10**9, 2)])
+def test_window_equals_global_index_product(name, make, C, sigma, vec):
+    A = make()
+    x = synth.uniform(A.ncols, 31, 1)
+    on = build(A, C, sigma, vec=vec, xwindow=1)
+    off = build(A, C, sigma, vec=vec, xwindow=-1)
+    inf = on.info
+    say("xwindow", name, "C", C, "sigma", sigma, "vec", inf["vec"], "window", inf["xwindow_max"], "segments",
+        inf["xsegments"])
+    assert inf["xwindow"] == 1 and off.info["xwindow"] == 0
+    y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
+    assert np.array_equal(y_on.view(np.uint64), y_off.view(np.uint64))
+    check_fp64(A, y_on, x)
+    assert_layout_equal(A, on, C, sigma)
+
+
+@pytest.mark.parametrize("val_dtype,acc", [("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")])
+@pytest.mark.parametrize("C", [32, 64])
+def test_window_reduced_precision_bitwise(val_dtype, acc, C):
+    A = synth.stencil27(20)
+    x = oracle.round_f32(synth.uniform(A.ncols, 32, 1)).astype(np.float64)
+    on = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, xwindow=1)
+    off = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, xwindow=-1)
+    assert on.info["xwindow"] == 1
+    y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
+    assert np.array_equal(y_on, y_off)
+
+
+def test_window_symmetric_mode():
+    import torch
+    from paper_1307_6209_amd import sellcs
+    A = synth.stencil27(16)
+    x = synth.uniform(A.ncols, 33, 1)
+    hs = [build(A, 32, 256, permute_columns=True, xwindow=w) for w in (1, -1)]
+    assert hs[0].info["xwindow"] == 1
+    ys = []
+    for h in hs:
+        xd = torch.from_numpy(x).cuda()
+        xp, yp = torch.empty_like(xd), torch.empty_like(xd)
+        y = torch.empty_like(xd)
+        sellcs.sell_permute(h, xd, xp)
+        sellcs.sell_spmv(h, xp, yp)
+        sellcs.sell_unpermute(h, yp, y)
+        torch.cuda.synchronize()
+        ys.append(y.cpu().numpy())
+    assert np.array_equal(ys[0], ys[1])
+    check_fp64(A, ys[0], x)
+
+
+def test_window_auto_falls_back_and_required_is_refused():
+    from paper_1307_6209_amd import sellcs
+    P = synth.powerlaw(40_000, seed=8)  # uniform half of the columns: windows far too large
+    h = build(P, 32, 1)
+    assert h.info["xwindow"] == 0
+    with pytest.raises(sellcs.SellError) as e:
+        build(P, 32, 1, xwindow=1)
+    assert e.value.status == sellcs.SELL_ERR_UNSUPPORTED
+    S = synth.stencil27(12)
+    for kw in ({"C": 128}, {"C": 32, "vec": 4}, {"C": 4}):
+        C = kw.pop("C")
+        with pytest.raises(sellcs.SellError):
+            build(S, C, 1, xwindow=1, **kw)
+        assert build(S, C, 1, **kw).info["xwindow"] == 0  # auto: the plain kernel
+    # the default build of a banded matrix uses the window
+    assert build(S, 32, 1).info["xwindow"] == 1
+
+
+def test_window_ragged_groups_and_empty_rows():
+    """Row counts that leave the last group of chunks short, empty rows and
+    empty chunks."""
+    for n in (1, 31, 33, 129, 1000):
+        A = banded(n, n, half=5, max_len=8)
+        x = synth.uniform(A.ncols, 34, 1)
+        for C in (8, 32, 64):
+            on = build(A, C, 1, xwindow=0)
+            off = build(A, C, 1, xwindow=-1)
+            if A.nnz == 0:
+                continue
+            assert on.info["xwindow"] == 1, (n, C)
+            assert np.array_equal(spmv_gpu(on, x).view(np.uint64), spmv_gpu(off, x).view(np.uint64))

@@ -48,3 +48,14 @@ def test_algorithmic_bytes_27pt():
     n, padded = 160 ** 3, 109_672_320
     nb = model.algorithmic_bytes(n, n, padded, n // 32, 1, model.sizes_for("f64", "f64", False))
     assert nb == 12 * padded + 8 * n + 8 * n + 12 * (n // 32)
+
+
+def test_window_sizes():
+    """With the x window the streamed index is 2 bytes and each chunk carries
+    its share of the window tables (8 bytes per group of 4 chunks, 12 per
+    segment)."""
+    s = model.sizes_for("f64", "f64", False, xwindow=True, segments_per_chunk=2.5)
+    assert (s.sv, s.si, s.sx, s.sy, s.sp) == (8, 2, 8, 8, 0)
+    assert s.meta == 12 + 2 + 30
+    b = model.algorithmic_bytes(100, 100, 1000, 10, 1, s)
+    assert b == 10 * 1000 + 8 * 100 + 8 * 100 + 44 * 10
