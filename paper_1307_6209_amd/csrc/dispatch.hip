@@ -5,7 +5,7 @@ namespace sell {
 
 #define SELL_DECL(lc)                                                                 \
   hipError_t launch_spmv_##lc(int C, int U, int V, bool sz, const SpmvArgs &a, hipStream_t s);      \
-  hipError_t launch_spmv_xw_##lc(int C, int V, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s); \
+  hipError_t launch_spmv_xw_##lc(int C, int V, int U, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s); \
   hipError_t launch_batch_##lc(int C, int U, const BatchArgs &a, hipStream_t s); \
   int batch_waves_per_cu_##lc(int C, int U);
 SELL_DECL(f64_f64)
@@ -26,14 +26,14 @@ hipError_t launch_spmv(int combo, int C, int U, int V, bool sz, const SpmvArgs &
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_xw(int combo, int C, int V, const SpmvArgs &a, const XwArgs &w, size_t lds,
+hipError_t launch_spmv_xw(int combo, int C, int V, int U, const SpmvArgs &a, const XwArgs &w, size_t lds,
                           hipStream_t s) {
   switch (combo) {
-    case COMBO_F64_F64: return launch_spmv_xw_f64_f64(C, V, a, w, lds, s);
-    case COMBO_F32_F32: return launch_spmv_xw_f32_f32(C, V, a, w, lds, s);
-    case COMBO_F32_F64: return launch_spmv_xw_f32_f64(C, V, a, w, lds, s);
-    case COMBO_BF16_F32: return launch_spmv_xw_bf16_f32(C, V, a, w, lds, s);
-    case COMBO_BF16_F64: return launch_spmv_xw_bf16_f64(C, V, a, w, lds, s);
+    case COMBO_F64_F64: return launch_spmv_xw_f64_f64(C, V, U, a, w, lds, s);
+    case COMBO_F32_F32: return launch_spmv_xw_f32_f32(C, V, U, a, w, lds, s);
+    case COMBO_F32_F64: return launch_spmv_xw_f32_f64(C, V, U, a, w, lds, s);
+    case COMBO_BF16_F32: return launch_spmv_xw_bf16_f32(C, V, U, a, w, lds, s);
+    case COMBO_BF16_F64: return launch_spmv_xw_bf16_f64(C, V, U, a, w, lds, s);
   }
   return hipErrorInvalidValue;
 }

@@ -152,7 +152,7 @@ hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
 // Product with the x window staged in LDS (C in 8..64, V 1 or 2, no split
 // chunks); lds_bytes: the largest window times the x element size, rounded
 // up to 8 bytes, plus 8 bytes per segment of the largest segment table.
-hipError_t launch_spmv_xw(int combo, int C, int V, const SpmvArgs &a, const XwArgs &w, size_t lds_bytes,
+hipError_t launch_spmv_xw(int combo, int C, int V, int U, const SpmvArgs &a, const XwArgs &w, size_t lds_bytes,
                           hipStream_t s);
 hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, hipStream_t s);
 // Resident waves per CU of the batched kernel (persistent grid size).

@@ -6,8 +6,9 @@ namespace sell {
 hipError_t launch_spmv_f64_f64(int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s) {
   return dev::launch_spmv_t<COMBO_F64_F64>(C, U, V, skip_zero, a, s);
 }
-hipError_t launch_spmv_xw_f64_f64(int C, int V, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
-  return dev::launch_spmv_xw_t<COMBO_F64_F64>(C, V, a, w, lds, s);
+hipError_t launch_spmv_xw_f64_f64(int C, int V, int U, const SpmvArgs &a, const XwArgs &w, size_t lds,
+                               hipStream_t s) {
+  return dev::launch_spmv_xw_t<COMBO_F64_F64>(C, V, U, a, w, lds, s);
 }
 hipError_t launch_batch_f64_f64(int C, int U, const BatchArgs &a, hipStream_t s) {
   return dev::launch_batch_t<COMBO_F64_F64>(C, U, a, s);

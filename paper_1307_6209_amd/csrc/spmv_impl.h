@@ -643,18 +643,20 @@ hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a
   return skip_zero ? launch_spmv_zs<COMBO, true>(C, U, VV, a, s) : launch_spmv_zs<COMBO, false>(C, U, VV, a, s);
 }
 
-// C in {8, 16, 32, 64}; V = 1 with 4 steps in flight, V = 2 with 2.
+// C in {8, 16, 32, 64}; U * V slots in flight per lane: 4 or 8.
 template <int COMBO>
-hipError_t launch_spmv_xw_t(int C, int VV, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
+hipError_t launch_spmv_xw_t(int C, int VV, int U, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
   if (a.nwork <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((a.nwork + kXwChunks - 1) / kXwChunks);
 #define SELL_L(CC, VVV, UU)                                                                                    \
-  if (C == CC && VV == VVV) {                                                                                  \
+  if (C == CC && VV == VVV && U == UU) {                                                                       \
     hipLaunchKernelGGL((k_spmv_xw<COMBO, CC, VVV, UU>), dim3(nb), dim3(64 * kWavesPerBlock), lds, s, a, w);   \
     return hipGetLastError();                                                                                  \
   }
   SELL_L(8, 1, 4) SELL_L(16, 1, 4) SELL_L(32, 1, 4) SELL_L(64, 1, 4)
+  SELL_L(8, 1, 8) SELL_L(16, 1, 8) SELL_L(32, 1, 8) SELL_L(64, 1, 8)
   SELL_L(8, 2, 2) SELL_L(16, 2, 2) SELL_L(32, 2, 2) SELL_L(64, 2, 2)
+  SELL_L(8, 2, 4) SELL_L(16, 2, 4) SELL_L(32, 2, 4) SELL_L(64, 2, 4)
 #undef SELL_L
   return hipErrorInvalidValue;
 }
