@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-forms", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed headline products (for a kernel trace of exactly that kernel)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a few products and one copy probe")
     ap.add_argument("--sigma-sweep", action="store_true", help="SELL-32-sigma sweep on the power-law matrix")
@@ -440,6 +442,7 @@ def main():
                    "format": "SELL-%d-%d" % (HEADLINE["C"], HEADLINE["sigma"]), "beta": round(inf["beta"], 6),
                    "padded_slots": inf["padded"],
                    "index": "uint16 window positions (x window staged in LDS)" if inf["xwindow"] else "int32",
+                   "x_window_segments": inf["xsegments"], "x_window_max_elements": inf["xwindow_max"],
                    "values": "f64", "x": "f64", "y": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
@@ -449,6 +452,10 @@ def main():
         "probes": probes,
         "kernel_source_hash": src_hash,
     }
+    if args.headline_only:
+        h.close()
+        print(json.dumps(line))
+        return
     # precision forms on the same matrix, at the headline C and at C = 64, with
     # the normwise error against the FP64 product of the same rounded x
     forms, errs = {}, {}

@@ -93,7 +93,8 @@ typedef struct {
                            LDS once and the slots also store their 16-bit
                            position in it (2 bytes streamed instead of 4, x read
                            from LDS; same result bit for bit). 0: used when it
-                           fits (C in 8..64, vec 1 or 2, no split chunks, at most
+                           fits and the matrix has at least two groups per
+                           compute unit (C in 8..64, vec 1 or 2, no split chunks, at most
                            8192 slots and 1024 runs of consecutive columns per
                            group, window <= 16 KiB); -1: never;
                            1: required (SELL_ERR_UNSUPPORTED when it cannot be

@@ -379,8 +379,13 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
   // x windows for LDS staging: when they fit (xwindow 0) or required (1)
   if (o.xwindow >= 0) {
     const int V = g.V;
+    const int64_t ngroups_all = (nc + sell::kXwChunks - 1) / sell::kXwChunks;
     const bool shape_ok = C >= 8 && C <= 64 && (V == 1 || V == 2) && !h->units && h->padded > 0;
-    if (!shape_ok) {
+    // automatic mode skips small matrices: with fewer than two workgroups per
+    // CU the product is latency-bound and the staging round trip only adds
+    // to it (the 128^2 Laplacian: 2.4 us per call without, 3.1 with)
+    const bool big_enough = o.xwindow == 1 || ngroups_all >= 2 * (int64_t)di.cus;
+    if (!shape_ok || !big_enough) {
       if (o.xwindow == 1)
         return fail(SELL_ERR_UNSUPPORTED, "sell_build: the x window needs C in 8..64, vec 1 or 2 and no split chunks");
     } else {

@@ -104,8 +104,10 @@ def test_window_auto_falls_back_and_required_is_refused():
         with pytest.raises(sellcs.SellError):
             build(S, C, 1, xwindow=1, **kw)
         assert build(S, C, 1, **kw).info["xwindow"] == 0  # auto: the plain kernel
-    # the default build of a banded matrix uses the window
-    assert build(S, 32, 1).info["xwindow"] == 1
+    # the default build uses the window on a banded matrix with enough groups
+    # of chunks (two per compute unit), not on a small one
+    assert build(S, 32, 1).info["xwindow"] == 0
+    assert build(synth.stencil27(64), 32, 1).info["xwindow"] == 1
 
 
 def test_window_ragged_groups_and_empty_rows():
@@ -114,10 +116,10 @@ def test_window_ragged_groups_and_empty_rows():
     for n in (1, 31, 33, 129, 1000):
         A = banded(n, n, half=5, max_len=8)
         x = synth.uniform(A.ncols, 34, 1)
+        if A.nnz == 0:
+            continue
         for C in (8, 32, 64):
-            on = build(A, C, 1, xwindow=0)
+            on = build(A, C, 1, xwindow=1)
             off = build(A, C, 1, xwindow=-1)
-            if A.nnz == 0:
-                continue
             assert on.info["xwindow"] == 1, (n, C)
             assert np.array_equal(spmv_gpu(on, x).view(np.uint64), spmv_gpu(off, x).view(np.uint64))
