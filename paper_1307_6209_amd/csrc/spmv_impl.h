@@ -234,11 +234,10 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
 // sum: the result equals the global-index product bit for bit) with x read
 // from LDS.
 template <int COMBO, int C, int VV, int U>
-__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv_xw(SpmvArgs a, XwArgs xa) {
+__global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs xa) {
   using V = typename Types<COMBO>::V;
   using X = typename Types<COMBO>::X;
   using A = typename Types<COMBO>::A;
-  static_assert(kXwChunks == kWavesPerBlock, "one chunk per wave");
   static_assert(C <= 64 && C % VV == 0, "one wave covers a chunk");
   constexpr int T = 64 * VV / C;           // chunk columns per wave step
   constexpr int LPC = C / VV;              // lanes covering one chunk column
@@ -276,16 +275,16 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv_xw(SpmvArgs a, XwA
     int2 *segt = reinterpret_cast<int2 *>(xw_lds + (((size_t)xa.wcap * sizeof(X) + 7) & ~(size_t)7));
     const int64_t s0 = xa.segoff[g];
     const int ns = (int)(xa.segoff[g + 1] - s0);
-    for (int k = threadIdx.x; k < ns; k += 64 * kWavesPerBlock)
+    for (int k = threadIdx.x; k < ns; k += 64 * kXwChunks)
       segt[k] = make_int2(xa.seg[3 * (s0 + k)], xa.seg[3 * (s0 + k) + 1]);
     const int nwin = ns > 0 ? xa.seg[3 * (s0 + ns - 1) + 1] + xa.seg[3 * (s0 + ns - 1) + 2] : 0;
     __syncthreads();
     constexpr int K = 8;
-    for (int b = 0; b < nwin; b += 64 * kWavesPerBlock * K) {
+    for (int b = 0; b < nwin; b += 64 * kXwChunks * K) {
       X tmp[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int i = b + k * 64 * kWavesPerBlock + (int)threadIdx.x;
+        const int i = b + k * 64 * kXwChunks + (int)threadIdx.x;
         tmp[k] = (X)0;
         if (i < nwin) {
           int lo = 0, hi = ns - 1;  // last segment with position <= i
@@ -299,7 +298,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv_xw(SpmvArgs a, XwA
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int i = b + k * 64 * kWavesPerBlock + (int)threadIdx.x;
+        const int i = b + k * 64 * kXwChunks + (int)threadIdx.x;
         if (i < nwin) xw[i] = tmp[k];
       }
     }
@@ -650,7 +649,7 @@ hipError_t launch_spmv_xw_t(int C, int VV, int U, const SpmvArgs &a, const XwArg
   const unsigned nb = (unsigned)((a.nwork + kXwChunks - 1) / kXwChunks);
 #define SELL_L(CC, VVV, UU)                                                                                    \
   if (C == CC && VV == VVV && U == UU) {                                                                       \
-    hipLaunchKernelGGL((k_spmv_xw<COMBO, CC, VVV, UU>), dim3(nb), dim3(64 * kWavesPerBlock), lds, s, a, w);   \
+    hipLaunchKernelGGL((k_spmv_xw<COMBO, CC, VVV, UU>), dim3(nb), dim3(64 * kXwChunks), lds, s, a, w);        \
     return hipGetLastError();                                                                                  \
   }
   SELL_L(8, 1, 4) SELL_L(16, 1, 4) SELL_L(32, 1, 4) SELL_L(64, 1, 4)
