@@ -73,7 +73,8 @@ typedef struct {
   int32_t unroll;       /* matrix slots in flight per lane: 0 auto, else 4 or 8 */
   int32_t vec;          /* consecutive slots (rows) each lane loads at once: 0 auto
                            (2 for F64 values with >= 8 nonzeros per row on average,
-                           else 1), else 1, 2 or 4 (2 and 4 need C <= 64 and vec <= C) */
+                           and for F32/BF16 values when the x window is used; else
+                           1), else 1, 2 or 4 (2 and 4 need C <= 64 and vec <= C) */
   int32_t seg_cols;     /* widest chunk one work unit covers, in chunk columns,
                            before the chunk is split across waves (rounded up to
                            a multiple of 64): 0 auto, < 0 never split */

@@ -428,6 +428,11 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
         h->nxseg = xs.nseg;
         h->xwin_max = xs.maxwin;
         h->xseg_max = xs.maxseg;
+        // with the window, FP32/BF16 values run faster with two slots per
+        // lane (measured on the 27-point stencil: BF16 at C = 64 2,524 ->
+        // 2,615 GF/s); the work plan (one item per chunk, nothing split)
+        // does not depend on it
+        if (o.vec == 0 && h->vdt != SELL_F64 && g.V == 1) h->g = sell::geom_of(C, 2);
       }
     }
   }

@@ -59,14 +59,24 @@ def test_window_equals_global_index_product(name, make, C, sigma, vec):
 
 @pytest.mark.parametrize("val_dtype,acc", [("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")])
 @pytest.mark.parametrize("C", [32, 64])
-def test_window_reduced_precision_bitwise(val_dtype, acc, C):
+@pytest.mark.parametrize("vec", [1, 2])
+def test_window_reduced_precision_bitwise(val_dtype, acc, C, vec):
     A = synth.stencil27(20)
     x = oracle.round_f32(synth.uniform(A.ncols, 32, 1)).astype(np.float64)
-    on = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, xwindow=1)
-    off = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, xwindow=-1)
-    assert on.info["xwindow"] == 1
+    on = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, vec=vec, xwindow=1)
+    off = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, vec=vec, xwindow=-1)
+    assert on.info["xwindow"] == 1 and on.info["vec"] == vec
     y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
     assert np.array_equal(y_on, y_off)
+
+
+def test_window_default_slots_per_lane():
+    """With the window, FP32/BF16 values default to two slots per lane; the
+    plain kernel keeps one."""
+    A = synth.stencil27(64)
+    assert build(A, 64, 1, val_dtype="bf16", acc_dtype="f32").info["vec"] == 2
+    assert build(A, 64, 1, val_dtype="bf16", acc_dtype="f32", xwindow=-1).info["vec"] == 1
+    assert build(A, 32, 1).info["vec"] == 2
 
 
 def test_window_symmetric_mode():
