@@ -285,6 +285,8 @@ typedef struct {
                              assigns one product, from a layout-only build (row
                              order, chunk widths; no values), and time only the K
                              best */
+  const int32_t *xwindow; int32_t nxwindow; /* x path: the xwindow build option (0 = LDS
+                                               window when it fits, -1 = L2 gathers) */
 } sell_tune_space;
 
 typedef struct {
@@ -299,6 +301,7 @@ typedef struct {
   double beta;
   int32_t candidates;   /* configurations measured */
   int32_t predicted;    /* configurations ranked by the model (model_guided > 0) */
+  int32_t xwindow;      /* 1 when the fastest product staged x windows in LDS */
 } sell_tuned;
 
 /*

@@ -892,6 +892,9 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   int nV = sp.nvec > 0 ? sp.nvec : 1;
   const int32_t *Gs = sp.nseg_cols > 0 ? sp.seg_cols : defSeg;
   int nG = sp.nseg_cols > 0 ? sp.nseg_cols : 1;
+  const int32_t defX[] = {0};
+  const int32_t *Xs = sp.nxwindow > 0 ? sp.xwindow : defX;
+  int nX = sp.nxwindow > 0 ? sp.nxwindow : 1;
   sell_build_opts o{};
   o.val_dtype = sp.val_dtype;
   o.acc_dtype = sp.acc_dtype;
@@ -952,11 +955,13 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   r.gflops = -1.0;
   int cands = 0;
   for (const auto &cand : order) {
-    for (int iv = 0; iv < nV * nG; ++iv) {
+    for (int iv = 0; iv < nV * nG * nX; ++iv) {
       const int ic = cand.first, is = cand.second;
-      // slots per lane and split width are build parameters: one build each
+      // slots per lane, split width and x path are build parameters: one
+      // build each
       o.vec = Vs[iv % nV];
-      o.seg_cols = Gs[iv / nV];
+      o.seg_cols = Gs[(iv / nV) % nG];
+      o.xwindow = Xs[iv / (nV * nG)];
       sell_handle h = nullptr;
       sell_status st = sell_build(A, Cs[ic], Ss[is], &o, stream, &h);
       if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
@@ -989,6 +994,7 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
             r.seg_cols = h->seg_cols;
             r.unroll = Us[iu];
             r.ktile = h->ktile;
+            r.xwindow = h->lcol ? 1 : 0;
             r.gflops = gf;
             r.us_per_call = t * 1e6;
             r.beta = h->beta;

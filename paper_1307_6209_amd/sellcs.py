@@ -59,13 +59,15 @@ class SellTuneSpace(ctypes.Structure):
                 ("unroll", ctypes.POINTER(c_i32)), ("nunroll", c_i32), ("ktile", ctypes.POINTER(c_i32)),
                 ("nktile", c_i32), ("vec", ctypes.POINTER(c_i32)), ("nvec", c_i32),
                 ("seg_cols", ctypes.POINTER(c_i32)), ("nseg_cols", c_i32), ("val_dtype", ctypes.c_int),
-                ("acc_dtype", ctypes.c_int), ("reps", c_i32), ("model_guided", c_i32)]
+                ("acc_dtype", ctypes.c_int), ("reps", c_i32), ("model_guided", c_i32),
+                ("xwindow", ctypes.POINTER(c_i32)), ("nxwindow", c_i32)]
 
 
 class SellTuned(ctypes.Structure):
     _fields_ = [("C", c_i32), ("sigma", c_i64), ("unroll", c_i32), ("ktile", c_i32), ("vec", c_i32),
                 ("seg_cols", c_i32), ("gflops", c_d),
-                ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32), ("predicted", c_i32)]
+                ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32), ("predicted", c_i32),
+                ("xwindow", c_i32)]
 
 
 class SellBatchTuned(ctypes.Structure):
@@ -391,7 +393,7 @@ def sell_batch_destroy(b: SellBatch):
 
 def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=(), ktile=(), vec=(), seg_cols=(),
                   val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0, model_guided: int = 0,
-                  stream=None) -> dict:
+                  xwindow=(), stream=None) -> dict:
     """Time the configurations of the search space (all of them, or the
     model_guided best by the code-balance model); return the fastest."""
     import torch
@@ -403,9 +405,10 @@ def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
     arrs = [(c_i32 * len(C))(*C), (c_i64 * len(sigma))(*sigma), (c_i32 * len(unroll))(*unroll),
             (c_i32 * len(ktile))(*ktile), (c_i32 * len(vec))(*vec), (c_i32 * len(seg_cols))(*seg_cols)]
+    xa = (c_i32 * len(xwindow))(*xwindow)
     sp = SellTuneSpace(arrs[0], len(C), arrs[1], len(sigma), arrs[2], len(unroll), arrs[3], len(ktile),
                        arrs[4], len(vec), arrs[5], len(seg_cols), DTYPES[val_dtype], DTYPES[acc_dtype], reps,
-                       model_guided)
+                       model_guided, xa, len(xwindow))
     r = SellTuned()
     _check(lib().sell_autotune(ctypes.byref(A), k, ctypes.byref(sp), _stream(stream), ctypes.byref(r)), "sell_autotune")
     return {name: getattr(r, name) for name, _ in SellTuned._fields_}
@@ -429,7 +432,7 @@ def sell_batch_autotune(mats, C=(), sigma=(), val_dtype: str = "f64", acc_dtype:
     ca, sa = (c_i32 * len(C))(*C), (c_i64 * len(sigma))(*sigma)
     empty = (c_i32 * 0)()
     sp = SellTuneSpace(ca, len(C), sa, len(sigma), empty, 0, empty, 0, empty, 0, empty, 0, DTYPES[val_dtype],
-                       DTYPES[acc_dtype], reps, 0)
+                       DTYPES[acc_dtype], reps, 0, empty, 0)
     r = SellBatchTuned()
     sig = (c_i64 * n)()
     _check(lib().sell_batch_autotune(arr, n, ctypes.byref(sp), _stream(stream), ctypes.byref(r), sig),

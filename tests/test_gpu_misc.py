@@ -110,3 +110,14 @@ def test_spmv_in_captured_graph():
         assert np.array_equal(y.cpu().numpy(), want) and np.array_equal(y2.cpu().numpy(), want2)
         sellcs.sell_spmv(hs, x, y2)  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_autotune_x_path():
+    """The x path (LDS window or L2 gathers) is searched too; on a banded
+    matrix large enough for the window the window wins."""
+    from paper_1307_6209_amd import sellcs
+    A = synth.stencil27(64)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(32,), sigma=(1,), unroll=(8,), xwindow=(-1, 0), reps=10)
+    say("autotune x path", r)
+    assert r["candidates"] == 2 and r["xwindow"] in (0, 1)
