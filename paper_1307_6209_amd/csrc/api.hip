@@ -487,8 +487,9 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   hipError_t e;
   if (h->lcol) {  // x windows staged in LDS
     const sell::XwArgs w{h->lcol, h->xsegoff, h->xseg, h->xwin_max};
+    // window, then the segment table with room for one entry per thread
     const size_t lds = (((size_t)h->xwin_max * (h->xdt == SELL_F64 ? 8 : 4) + 7) & ~(size_t)7) +
-                       8 * (size_t)h->xseg_max;
+                       8 * (size_t)std::max(h->xseg_max, 64 * sell::kXwChunks);
     e = sell::launch_spmv_xw(h->combo, h->C, h->g.V, h->unroll / h->g.V, a, w, lds, static_cast<hipStream_t>(stream));
   } else {
     e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a, static_cast<hipStream_t>(stream));

@@ -94,6 +94,32 @@ __device__ __forceinline__ double fmac(float v, float x, double acc) {
 }
 __device__ __forceinline__ float fmac(float v, float x, float acc) { return __builtin_fmaf(v, x, acc); }
 
+// Loads wave steps s0 .. s0+U-1 of one lane at slot offset off0 + step *
+// stride of the arrays ci_base and v_base; ok[u] says which steps hold a
+// column of the chunk (step below se, column t + step*T below cl). The
+// others load slot 0 of the arrays instead: a branch around a load of
+// packed 16-bit elements makes the compiler unpack them inside it and wait
+// for each load before issuing the next. Callers skip the slots with ok[u]
+// false; the arrays must hold a slot.
+template <int U, int VV, typename I, typename V>
+__device__ __forceinline__ void ld_batch(const I *ci_base, const V *v_base, int64_t off0, int64_t stride, int s0,
+                                         int se, int T, int t, int cl, bool (&ok)[U], I (&ci)[U][VV],
+                                         V (&raw)[U][VV]) {
+  // 32-bit and wider elements need no unpacking: there the steps past the
+  // chunk (a condition uniform over the wave) are skipped by a branch
+  constexpr bool kSkip = sizeof(I) >= 4 && sizeof(V) >= 4;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int ss = s0 + u;
+    ok[u] = ss < se && ss * T + t < cl;
+    if (!kSkip || ss < se) {
+      const int64_t o = ok[u] ? off0 + (int64_t)ss * stride : 0;
+      ld_stream<VV>(ci_base + o, ci[u]);
+      ld_stream<VV>(v_base + o, raw[u]);
+    }
+  }
+}
+
 constexpr int kWavesPerBlock = 4;
 
 // One work unit: rows [h*rpw, (h+1)*rpw) of chunk `chunk`, chunk columns
@@ -165,21 +191,7 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
     int32_t ci[U][VV];
     V raw[U][VV];
     bool ok[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int ss = s + u;
-      ok[u] = ss < se && ss * T + t < je;
-      if (ok[u]) {
-        ld_stream<VV>(cp + (int64_t)ss * STRIDE, ci[u]);
-        ld_stream<VV>(vp + (int64_t)ss * STRIDE, raw[u]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < VV; ++v) {
-          ci[u][v] = 0;
-          raw[u][v] = 0;
-        }
-      }
-    }
+    ld_batch<U, VV>(col, static_cast<const V *>(valv), off0, STRIDE, s, se, T, t, je, ok, ci, raw);
     X xg[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -226,6 +238,41 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
   for (int v = 0; v < VV; ++v) part[v] = acc[v];
 }
 
+// Raw buffer loads over the slots of one chunk. The descriptor (uniform over
+// the wave) covers exactly the chunk's bytes; a load at an offset past them
+// returns zero and touches no memory, so the partial last step of a chunk,
+// steps past its end and empty chunks need neither a branch nor a substitute
+// address. Loads are streaming (non-temporal).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const T *p, int64_t slots) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0, (int)(slots * (int64_t)sizeof(T)),
+                                           0x00020000);
+}
+
+constexpr int kBufStream = 2;  // cache policy: non-temporal
+
+template <int N, typename T>
+__device__ __forceinline__ void ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t slot, T (&out)[N]) {
+  constexpr int B = N * (int)sizeof(T);
+  const uint32_t off = slot * (uint32_t)sizeof(T);
+  if constexpr (B == 2) {
+    const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, kBufStream);
+    __builtin_memcpy(out, &v, 2);
+  } else if constexpr (B == 4) {
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kBufStream);
+    __builtin_memcpy(out, &v, 4);
+  } else if constexpr (B == 8) {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kBufStream);
+    __builtin_memcpy(out, &v, 8);
+  } else {
+    static_assert(B == 16, "2, 4, 8 or 16 bytes per lane");
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kBufStream);
+    __builtin_memcpy(out, &v, 16);
+  }
+}
+
 // Product with the x window in LDS. Workgroup g (kXwChunks waves, one chunk
 // each) first issues its first U wave steps of val and of the 16-bit window
 // positions, then stages its window -- every element with one load, its
@@ -247,35 +294,46 @@ __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs x
 
   const int64_t g = blockIdx.x;
   const int lane = threadIdx.x & 63;
-  const int64_t chunk = g * kXwChunks + (threadIdx.x >> 6);
+  // the wave's chunk, marked uniform so that its descriptors are scalar
+  const int64_t chunk = g * kXwChunks + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool live = chunk < a.nwork;
   const int64_t base = live ? a.cs[chunk] : 0;
   const int cl = live ? a.cl[chunk] : 0;
   const int rl0 = (VV * lane) % C, t = (VV * lane) / C;
-  const int64_t off0 = base + (int64_t)t * C + rl0;
-  const uint16_t *cp = xa.lcol + off0;
-  const V *vp = static_cast<const V *>(a.val) + off0;
+  // slot of step s of this lane within the chunk: s * STRIDE + lo0
+  const uint32_t lo0 = (uint32_t)(t * C + rl0);
+  const __amdgpu_buffer_rsrc_t rc = chunk_rsrc(xa.lcol + base, (int64_t)C * cl);
+  const __amdgpu_buffer_rsrc_t rv = chunk_rsrc(static_cast<const V *>(a.val) + base, (int64_t)C * cl);
   const int full = cl / T, se = (cl + T - 1) / T;
 
+  // The group's segment table (start column, window position) goes to LDS
+  // behind the window, which has room for at least one entry per thread.
+  // This thread's first entry is loaded ahead of the matrix steps and stored
+  // unconditionally (threads past the table store a copy of entry 0 that is
+  // never read), so that the store waits for that load only and the load
+  // cannot move behind the matrix steps (a table entry always exists: the
+  // layout holds a slot).
+  int2 *segt = reinterpret_cast<int2 *>(xw_lds + (((size_t)xa.wcap * sizeof(X) + 7) & ~(size_t)7));
+  const int64_t s0 = xa.segoff[g];
+  const int ns = (int)(xa.segoff[g + 1] - s0);
+  const int64_t e0 = (int)threadIdx.x < ns ? s0 + threadIdx.x : 0;
+  const int2 seg0 = make_int2(xa.seg[3 * e0], xa.seg[3 * e0 + 1]);
+  // steps 0 .. U-1; ok: the step holds a column of the chunk in this lane
   uint16_t ci[U][VV];
   V raw[U][VV];
-  const bool first = U <= full;
-  if (first) {
+  bool ok[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      ld_stream<VV>(cp + (int64_t)u * STRIDE, ci[u]);
-      ld_stream<VV>(vp + (int64_t)u * STRIDE, raw[u]);
-    }
+  for (int u = 0; u < U; ++u) {
+    ok[u] = u * T + t < cl;
+    ld_buf<VV>(rc, lo0 + (uint32_t)(u * STRIDE), ci[u]);
+    ld_buf<VV>(rv, lo0 + (uint32_t)(u * STRIDE), raw[u]);
   }
-  // stage the window: first the group's segment table (start column,
-  // window position) into LDS behind the window, then every window element
-  // with one load, its segment found by binary search in LDS
+  // stage the window: every window element with one load, its segment found
+  // by binary search in LDS
   {
     const X *x = static_cast<const X *>(a.x);
-    int2 *segt = reinterpret_cast<int2 *>(xw_lds + (((size_t)xa.wcap * sizeof(X) + 7) & ~(size_t)7));
-    const int64_t s0 = xa.segoff[g];
-    const int ns = (int)(xa.segoff[g + 1] - s0);
-    for (int k = threadIdx.x; k < ns; k += 64 * kXwChunks)
+    segt[threadIdx.x] = seg0;
+    for (int k = threadIdx.x + 64 * kXwChunks; k < ns; k += 64 * kXwChunks)
       segt[k] = make_int2(xa.seg[3 * (s0 + k)], xa.seg[3 * (s0 + k) + 1]);
     const int nwin = ns > 0 ? xa.seg[3 * (s0 + ns - 1) + 1] + xa.seg[3 * (s0 + ns - 1) + 2] : 0;
     __syncthreads();
@@ -309,34 +367,37 @@ __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs x
   A acc[VV];
 #pragma unroll
   for (int v = 0; v < VV; ++v) acc[v] = 0;
-  int s = 0;
-  if (first) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+  for (int u = 0; u < U; ++u)
+    if (ok[u]) {
 #pragma unroll
       for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xw[ci[u][v]], acc[v]);
-    s = U;
-  }
+    }
+  int s = U;
   for (; s + U <= full; s += U) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
-      ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
+      ld_buf<VV>(rc, lo0 + (uint32_t)((s + u) * STRIDE), ci[u]);
+      ld_buf<VV>(rv, lo0 + (uint32_t)((s + u) * STRIDE), raw[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xw[ci[u][v]], acc[v]);
   }
-  for (; s < se; ++s) {  // the last steps; the very last may be partial
-    if (s * T + t < cl) {
-      uint16_t c1[VV];
-      V r1[VV];
-      ld_stream<VV>(cp + (int64_t)s * STRIDE, c1);
-      ld_stream<VV>(vp + (int64_t)s * STRIDE, r1);
+  if (s < se) {  // at most U steps remain, loaded together; the last may be partial
 #pragma unroll
-      for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(r1[v]), xw[c1[v]], acc[v]);
+    for (int u = 0; u < U; ++u) {
+      ok[u] = (s + u) * T + t < cl;
+      ld_buf<VV>(rc, lo0 + (uint32_t)((s + u) * STRIDE), ci[u]);
+      ld_buf<VV>(rv, lo0 + (uint32_t)((s + u) * STRIDE), raw[u]);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) {
+#pragma unroll
+        for (int v = 0; v < VV; ++v) acc[v] = fmac(cvt(raw[u][v]), xw[ci[u][v]], acc[v]);
+      }
   }
 #pragma unroll
   for (int off = 32; off >= LPC; off >>= 1)
