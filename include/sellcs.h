@@ -70,7 +70,10 @@ typedef struct {
 typedef struct {
   sell_dtype val_dtype; /* storage of the matrix values: F64, F32 or BF16 */
   sell_dtype acc_dtype; /* accumulation and y: F64 or F32 (F64 values need F64) */
-  int32_t unroll;       /* matrix slots in flight per lane: 0 auto, else 4 or 8 */
+  int32_t unroll;       /* matrix slots in flight per lane: 0 auto (16 for the x-window
+                           product with two slots per lane, else 8), or 4, 8 or 16
+                           (16 applies to the x-window product with two slots per
+                           lane; elsewhere it is taken as 8) */
   int32_t vec;          /* consecutive slots (rows) each lane loads at once: 0 auto
                            (2 for F64 values with >= 8 nonzeros per row on average,
                            and for F32/BF16 values when the x window is used; else
@@ -116,7 +119,7 @@ typedef struct {
   int64_t max_row_len;
   sell_dtype val_dtype, x_dtype, acc_dtype;
   int32_t lanes_per_row; /* lanes of one wavefront that share a row (64 / C, or 1) */
-  int32_t unroll;
+  int32_t unroll;        /* slots in flight per lane of the product that runs */
   int32_t vec;
   int32_t seg_cols;      /* split threshold in chunk columns */
   int64_t nunits;        /* work units of one sell_spmv launch */
@@ -272,7 +275,8 @@ sell_status sell_crs_spmv(const sell_crs *A, int32_t lanes_per_row, const double
 typedef struct {
   const int32_t *C;       int32_t nC;       /* chunk heights */
   const int64_t *sigma;   int32_t nsigma;   /* sorting scopes */
-  const int32_t *unroll;  int32_t nunroll;
+  const int32_t *unroll;  int32_t nunroll;  /* default 4, 8, 16 (16: x-window builds with
+                                               two slots per lane only) */
   const int32_t *ktile;   int32_t nktile;   /* used when k > 1 */
   const int32_t *vec;     int32_t nvec;     /* slots per lane (0 = default); with C this sets
                                                the lanes per row, 64 * vec / C */

@@ -280,6 +280,8 @@ __device__ __forceinline__ void ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t slot, 
 // spmv_unit (same lanes, same order of the multiply-adds, same cross-lane
 // sum: the result equals the global-index product bit for bit) with x read
 // from LDS.
+constexpr int64_t kXcdTile = 16;  // groups of chunks per XCD tile
+
 template <int COMBO, int C, int VV, int U>
 __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs xa) {
   using V = typename Types<COMBO>::V;
@@ -292,7 +294,16 @@ __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs x
   extern __shared__ unsigned char xw_lds[];
   X *xw = reinterpret_cast<X *>(xw_lds);
 
-  const int64_t g = blockIdx.x;
+  // Workgroup b runs on XCD b mod 8. Consecutive groups of chunks share
+  // most of their x lines, so each XCD takes tiles of kXcdTile consecutive
+  // groups (the last, partial round of tiles keeps the plain order): the
+  // staging loads find more of their lines in that XCD's L2.
+  int64_t g = blockIdx.x;
+  {
+    const int64_t nb = gridDim.x, xcd = g % 8, i = g / 8;
+    if (g < nb / (8 * kXcdTile) * (8 * kXcdTile))
+      g = (i / kXcdTile) * 8 * kXcdTile + xcd * kXcdTile + i % kXcdTile;
+  }
   const int lane = threadIdx.x & 63;
   // the wave's chunk, marked uniform so that its descriptors are scalar
   const int64_t chunk = g * kXwChunks + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -717,6 +728,7 @@ hipError_t launch_spmv_xw_t(int C, int VV, int U, const SpmvArgs &a, const XwArg
   SELL_L(8, 1, 8) SELL_L(16, 1, 8) SELL_L(32, 1, 8) SELL_L(64, 1, 8)
   SELL_L(8, 2, 2) SELL_L(16, 2, 2) SELL_L(32, 2, 2) SELL_L(64, 2, 2)
   SELL_L(8, 2, 4) SELL_L(16, 2, 4) SELL_L(32, 2, 4) SELL_L(64, 2, 4)
+  SELL_L(8, 2, 8) SELL_L(16, 2, 8) SELL_L(32, 2, 8) SELL_L(64, 2, 8)
 #undef SELL_L
   return hipErrorInvalidValue;
 }

@@ -71,8 +71,10 @@ def test_host_side_argument_errors(L):
     f64_val_f32_acc = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=1)  # FP64 values need FP64 accumulation
     assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(f64_val_f32_acc), None,
                         ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
-    badu = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, unroll=5)
-    assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badu), None, ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
+    for u in (5, 12, 32):
+        badu = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, unroll=u)
+        assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badu), None,
+                            ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
     for C, vec in [(128, 2), (2, 4), (32, 3)]:
         badv = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, vec=vec)
         assert L.sell_build(ctypes.byref(A), C, 1, ctypes.byref(badv), None,

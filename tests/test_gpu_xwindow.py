@@ -72,11 +72,39 @@ def test_window_reduced_precision_bitwise(val_dtype, acc, C, vec):
 
 def test_window_default_slots_per_lane():
     """With the window, FP32/BF16 values default to two slots per lane; the
-    plain kernel keeps one."""
+    plain kernel keeps one. With two slots per lane the window kernel keeps
+    sixteen in flight (eight wave steps) by default; the plain kernel takes
+    an unroll of 16 as 8."""
     A = synth.stencil27(64)
-    assert build(A, 64, 1, val_dtype="bf16", acc_dtype="f32").info["vec"] == 2
-    assert build(A, 64, 1, val_dtype="bf16", acc_dtype="f32", xwindow=-1).info["vec"] == 1
-    assert build(A, 32, 1).info["vec"] == 2
+    on = build(A, 64, 1, val_dtype="bf16", acc_dtype="f32").info
+    assert on["vec"] == 2 and on["unroll"] == 16
+    off = build(A, 64, 1, val_dtype="bf16", acc_dtype="f32", xwindow=-1).info
+    assert off["vec"] == 1 and off["unroll"] == 8
+    assert build(A, 32, 1).info["vec"] == 2 and build(A, 32, 1).info["unroll"] == 16
+    assert build(A, 32, 1, unroll=16, xwindow=-1).info["unroll"] == 8
+    assert build(A, 32, 1, unroll=16, vec=1).info["unroll"] == 8
+    assert build(A, 32, 1, unroll=4).info["unroll"] == 4
+
+
+@pytest.mark.parametrize("C", [8, 16, 32, 64])
+@pytest.mark.parametrize("unroll", [4, 8, 16])
+@pytest.mark.parametrize("val_dtype,acc", [("f64", "f64"), ("bf16", "f32")])
+def test_window_unroll_equals_global_index_product(C, unroll, val_dtype, acc):
+    """Every batch depth of the window kernel (two slots per lane) against
+    the global-index product: the same multiply-adds in the same order, so
+    the results agree bit for bit; a banded matrix with ragged rows leaves
+    partial last steps and chunks shorter than one batch."""
+    A = banded(2500, 11, half=30, max_len=30)
+    x = synth.uniform(A.ncols, 35, 1)
+    if val_dtype != "f64":
+        x = oracle.round_f32(x).astype(np.float64)
+    on = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, vec=2, unroll=unroll, xwindow=1)
+    off = build(A, C, 1, val_dtype=val_dtype, acc_dtype=acc, vec=2, xwindow=-1)
+    assert on.info["xwindow"] == 1 and on.info["unroll"] == unroll
+    y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
+    assert np.array_equal(y_on, y_off)
+    if val_dtype == "f64":
+        check_fp64(A, y_on, x)
 
 
 def test_window_symmetric_mode():
