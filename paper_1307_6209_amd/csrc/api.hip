@@ -529,9 +529,11 @@ extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: C must be >= 8 for k > 1");
   if (h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k exceeds the kmax given at build");
   int kv = choose_kv(h, k, h->ktile);
-  // the gathers of KV contiguous right-hand sides are vector accesses: keep
-  // them aligned (X rows are k doubles apart, k % kv == 0 by choose_kv)
-  while (kv > 1 && (reinterpret_cast<uintptr_t>(X) % (sizeof(double) * kv)) != 0) kv >>= 1;
+  // the gathers of KV contiguous right-hand sides and the stores of a lane's
+  // KV results are vector accesses: keep them aligned (rows of X and Y are k
+  // doubles apart, k % kv == 0 by choose_kv)
+  while (kv > 1 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % (sizeof(double) * kv)) != 0)
+    kv >>= 1;
   const int KT = (64 / h->g.rpw) * kv;
   const int64_t ntiles = (k + KT - 1) / KT;
   if (h->units && ntiles * KT > next_pow2(h->kmax))

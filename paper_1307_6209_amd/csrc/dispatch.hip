@@ -72,7 +72,7 @@ hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((dev::k_spmmv<CC, KK>), dim3(nb, nt), dim3(64 * dev::kWavesPerBlock), 0, s, a);     \
     hipError_t e_ = hipGetLastError();                                                                      \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                       \
-    hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, nt), dim3(64), 0, s, a);          \
+    hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, nt), dim3(64 * KK), 0, s, a);     \
     return hipGetLastError();                                                                               \
   }
   SELL_L(8, 1) SELL_L(8, 2) SELL_L(8, 4) SELL_L(8, 8)

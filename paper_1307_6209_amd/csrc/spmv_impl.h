@@ -633,8 +633,17 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   if (nseg == 1) {
     if (active && p < a.nrows) {
       const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
+      // the KV results of a lane are contiguous and aligned (k % KV == 0,
+      // Y aligned to KV doubles): one vector store for KV <= 4 (measured
+      // faster there, slower for KV = 8 than eight single stores)
+      if constexpr (KV > 1 && KV <= 4) {
+        VecT o;
+        __builtin_memcpy(&o, acc, sizeof(o));
+        __builtin_nontemporal_store(o, reinterpret_cast<VecT *>(Y + row * k + v0));
+      } else {
 #pragma unroll
-      for (int v = 0; v < KV; ++v) __builtin_nontemporal_store(acc[v], Y + row * k + v0 + v);
+        for (int v = 0; v < KV; ++v) __builtin_nontemporal_store(acc[v], Y + row * k + v0 + v);
+      }
     }
     return;
   }
@@ -649,9 +658,11 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
 }
 
 // Block form: add the segment sums of split row slices. Block (w, tile):
-// split slice w, pass tile; lanes cover RPW rows x KT right-hand sides.
+// split slice w, pass tile; one thread per (row, right-hand side) of the
+// slice (RPW * KT = 64 * KV threads), the segment sums added in segment
+// order with eight loads in flight.
 template <int C>
-__global__ void __launch_bounds__(64) k_combine_mm(SpmvArgs a) {
+__global__ void __launch_bounds__(512) k_combine_mm(SpmvArgs a) {
   constexpr int RPW = C < 64 ? C : 64;
   constexpr int WPC = C > 64 ? C / 64 : 1;
   const SplitDesc d = a.splits[blockIdx.x];
@@ -660,13 +671,23 @@ __global__ void __launch_bounds__(64) k_combine_mm(SpmvArgs a) {
   const int h = d.item - (int)(chunk * WPC);
   const double *base = static_cast<const double *>(a.partial) + (d.poff * ntiles + (int64_t)tile * d.nseg * RPW) * KT;
   double *Y = static_cast<double *>(a.y);
-  for (int e = threadIdx.x; e < RPW * KT; e += 64) {
+  for (int e = threadIdx.x; e < RPW * KT; e += blockDim.x) {
     const int rl = e / KT, vl = e - rl * KT;
     const int v = tile * KT + vl;
     const int64_t p = chunk * C + h * RPW + rl;
     if (v >= k || p >= a.nrows) continue;
+    const double *src = base + (int64_t)rl * KT + vl;
+    const int64_t step = (int64_t)RPW * KT;  // between the sums of two segments
     double sum = 0.0;
-    for (int q = 0; q < d.nseg; ++q) sum += base[((int64_t)q * RPW + rl) * KT + vl];
+    int q = 0;
+    for (; q + 8 <= d.nseg; q += 8) {
+      double t[8];
+#pragma unroll
+      for (int e8 = 0; e8 < 8; ++e8) t[e8] = src[(int64_t)(q + e8) * step];
+#pragma unroll
+      for (int e8 = 0; e8 < 8; ++e8) sum += t[e8];
+    }
+    for (; q < d.nseg; ++q) sum += src[(int64_t)q * step];
     const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
     Y[row * k + v] = sum;
   }
