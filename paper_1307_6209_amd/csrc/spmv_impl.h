@@ -30,6 +30,8 @@
 
 #include "sell_internal.h"
 
+#include <type_traits>
+
 namespace sell {
 namespace dev {
 
@@ -87,6 +89,7 @@ __device__ __forceinline__ int32_t ld_col(const int32_t *p) { return __builtin_n
 __device__ __forceinline__ double cvt(double v) { return v; }
 __device__ __forceinline__ float cvt(float v) { return v; }
 __device__ __forceinline__ float cvt(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float cvt(uint32_t b) { return __uint_as_float(b << 16); }  // bfloat16 bits held in 32
 
 __device__ __forceinline__ double fmac(double v, double x, double acc) { return __builtin_fma(v, x, acc); }
 __device__ __forceinline__ double fmac(float v, float x, double acc) {
@@ -96,18 +99,20 @@ __device__ __forceinline__ float fmac(float v, float x, float acc) { return __bu
 
 // Loads wave steps s0 .. s0+U-1 of one lane at slot offset off0 + step *
 // stride of the arrays ci_base and v_base; ok[u] says which steps hold a
-// column of the chunk (step below se, column t + step*T below cl). The
-// others load slot 0 of the arrays instead: a branch around a load of
-// packed 16-bit elements makes the compiler unpack them inside it and wait
-// for each load before issuing the next. Callers skip the slots with ok[u]
-// false; the arrays must hold a slot.
-template <int U, int VV, typename I, typename V>
+// column of the chunk (step below se, column t + step*T below cl), and the
+// lanes of a partial step past the chunk load slot 0 instead (callers skip
+// the slots with ok[u] false; the arrays must hold a slot). Steps past the
+// chunk (a condition uniform over the wave; on short chunks most of a
+// batch) are skipped by a branch, except where one lane holds two 16-bit
+// elements in a word: around such a load a branch makes the compiler unpack
+// the word inside it and wait for each load before issuing the next. Values
+// narrower than 32 bits are returned widened (R), so that the compiler does
+// not pack the values of several steps into shared registers either.
+template <int U, int VV, typename I, typename V, typename R>
 __device__ __forceinline__ void ld_batch(const I *ci_base, const V *v_base, int64_t off0, int64_t stride, int s0,
                                          int se, int T, int t, int cl, bool (&ok)[U], I (&ci)[U][VV],
-                                         V (&raw)[U][VV]) {
-  // 32-bit and wider elements need no unpacking: there the steps past the
-  // chunk (a condition uniform over the wave) are skipped by a branch
-  constexpr bool kSkip = sizeof(I) >= 4 && sizeof(V) >= 4;
+                                         R (&raw)[U][VV]) {
+  constexpr bool kSkip = VV == 1 || (sizeof(I) >= 4 && sizeof(V) >= 4);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int ss = s0 + u;
@@ -115,9 +120,21 @@ __device__ __forceinline__ void ld_batch(const I *ci_base, const V *v_base, int6
     if (!kSkip || ss < se) {
       const int64_t o = ok[u] ? off0 + (int64_t)ss * stride : 0;
       ld_stream<VV>(ci_base + o, ci[u]);
-      ld_stream<VV>(v_base + o, raw[u]);
+      V r[VV];
+      ld_stream<VV>(v_base + o, r);
+#pragma unroll
+      for (int v = 0; v < VV; ++v) raw[u][v] = (R)r[v];
     }
   }
+}
+
+// An empty statement that takes v in a register and may change it: the
+// compiler can no longer fold the conversions of v that follow into the
+// blocks that loaded it (a load in a per-step branch followed there by a
+// conversion makes the step wait for its own load before the next issues).
+template <typename T>
+__device__ __forceinline__ void opaque(T &v) {
+  asm volatile("" : "+v"(v));
 }
 
 constexpr int kWavesPerBlock = 4;
@@ -189,9 +206,18 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
   }
   if (s < se) {  // at most U steps remain; the last one may be partial
     int32_t ci[U][VV];
-    V raw[U][VV];
+    // one 16-bit value per lane is held in 32 bits (cvt takes either)
+    using R = typename std::conditional<sizeof(V) < 4 && VV == 1, uint32_t, V>::type;
+    R raw[U][VV];
     bool ok[U];
     ld_batch<U, VV>(col, static_cast<const V *>(valv), off0, STRIDE, s, se, T, t, je, ok, ci, raw);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < VV; ++v) {
+        opaque(ci[u][v]);
+        opaque(raw[u][v]);
+      }
     X xg[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u)

@@ -161,3 +161,35 @@ def test_window_ragged_groups_and_empty_rows():
             off = build(A, C, 1, xwindow=-1)
             assert on.info["xwindow"] == 1, (n, C)
             assert np.array_equal(spmv_gpu(on, x).view(np.uint64), spmv_gpu(off, x).view(np.uint64))
+
+
+def blocks_with_empty_runs(seed):
+    """Banded rows with runs of empty rows long enough to empty whole chunks
+    and whole groups of chunks, in the middle and at the end."""
+    A = banded(1400, seed, half=12, max_len=14)
+    lens = np.diff(A.rpt)
+    keep = np.ones(A.nrows, bool)
+    keep[300:760] = False      # 14+ chunks of 32 rows: several whole groups
+    keep[1100:1400] = False    # empty tail
+    keep[905] = False
+    rpt = np.zeros(A.nrows + 1, np.int64)
+    np.cumsum(np.where(keep, lens, 0), out=rpt[1:])
+    sel = np.repeat(keep, lens)
+    return synth.CRS(A.nrows, A.ncols, rpt, A.col[sel], A.val[sel])
+
+
+@pytest.mark.parametrize("C", [8, 32, 64])
+@pytest.mark.parametrize("unroll", [4, 16])
+def test_window_empty_chunks_and_groups(C, unroll):
+    """Live waves whose chunk holds no column read nothing and store zeros;
+    groups without a slot stage an empty window; the rest of the product is
+    untouched (bit-exact against the global-index product)."""
+    A = blocks_with_empty_runs(41)
+    x = synth.uniform(A.ncols, 36, 1)
+    on = build(A, C, 1, vec=2, unroll=unroll, xwindow=1)
+    off = build(A, C, 1, vec=2, xwindow=-1)
+    assert on.info["xwindow"] == 1
+    y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
+    assert np.array_equal(y_on.view(np.uint64), y_off.view(np.uint64))
+    assert np.all(y_on[300:760] == 0.0) and np.all(y_on[1100:] == 0.0) and y_on[905] == 0.0
+    check_fp64(A, y_on, x)
