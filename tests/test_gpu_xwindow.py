@@ -193,3 +193,37 @@ def test_window_empty_chunks_and_groups(C, unroll):
     assert np.array_equal(y_on.view(np.uint64), y_off.view(np.uint64))
     assert np.all(y_on[300:760] == 0.0) and np.all(y_on[1100:] == 0.0) and y_on[905] == 0.0
     check_fp64(A, y_on, x)
+
+
+def scattered_runs(n=66_000, run=60, ncols=1_000_000, seed=77):
+    """Each row holds `run` consecutive columns at a random offset: a group
+    of 4 chunks of 32 rows has a window of ~7,700 columns in 128 runs
+    (61 KB in FP64, above the automatic 16 KiB limit); 516 groups, more than
+    two per compute unit, so the window size alone decides the default."""
+    off = (synth.uniform(n, seed, 1, 0.0, 1.0) * (ncols - run)).astype(np.int64)
+    rpt = np.arange(n + 1, dtype=np.int64) * run
+    col = (off[:, None] + np.arange(run)[None, :]).reshape(-1).astype(np.int32)
+    val = synth.uniform(n * run, seed, 2)
+    return synth.CRS(n, ncols, rpt, col, val)
+
+
+@pytest.mark.parametrize("val_dtype,acc", [("f64", "f64"), ("f32", "f32")])
+def test_window_largest_required(val_dtype, acc):
+    """Windows beyond the automatic limit: the default build falls back to
+    the global-index product; xwindow = 1 builds them (up to 64 KiB of LDS)
+    and the product still equals the global-index one bit for bit."""
+    A = scattered_runs()
+    x = synth.uniform(A.ncols, 37, 1)
+    if val_dtype != "f64":
+        x = oracle.round_f32(x).astype(np.float64)
+    auto = build(A, 32, 1, val_dtype=val_dtype, acc_dtype=acc)
+    assert auto.info["xwindow"] == 0
+    on = build(A, 32, 1, val_dtype=val_dtype, acc_dtype=acc, vec=2, xwindow=1)
+    inf = on.info
+    say("largest window", val_dtype, inf["xwindow_max"], "segments", inf["xsegments"])
+    assert inf["xwindow"] == 1 and inf["xwindow_max"] > 7000
+    off = build(A, 32, 1, val_dtype=val_dtype, acc_dtype=acc, vec=2, xwindow=-1)
+    y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
+    assert np.array_equal(y_on, y_off)
+    if val_dtype == "f64":
+        check_fp64(A, y_on, x)
