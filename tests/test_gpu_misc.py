@@ -86,13 +86,17 @@ def test_spmv_in_captured_graph():
     rpt, col, val = dev_crs(A)
     h = sellcs.sell_build(rpt, col, val, A.ncols, 32, 1)
     hs = sellcs.sell_build(rpt, col, val, A.ncols, 16, A.nrows, seg_cols=64)
+    hw = sellcs.sell_build(rpt, col, val, A.ncols, 32, 1, xwindow=1)  # the x-window product
+    assert hw.info["xwindow"] == 1
     x = torch.from_numpy(synth.uniform(A.ncols, 75, 1)).cuda()
     y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
     y2 = torch.empty_like(y)
+    y3 = torch.empty_like(y)
     sellcs.sell_spmv(h, x, y)
     sellcs.sell_spmv(hs, x, y2)
+    sellcs.sell_spmv(hw, x, y3)
     torch.cuda.synchronize()
-    want, want2 = y.cpu().numpy().copy(), y2.cpu().numpy().copy()
+    want, want2, want3 = y.cpu().numpy().copy(), y2.cpu().numpy().copy(), y3.cpu().numpy().copy()
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -101,14 +105,18 @@ def test_spmv_in_captured_graph():
             for _ in range(5):
                 sellcs.sell_spmv(h, x, y)
                 sellcs.sell_spmv(hs, x, y2)
+                sellcs.sell_spmv(hw, x, y3)
     torch.cuda.current_stream().wait_stream(s)
     for rep in range(3):
         y.fill_(float("nan"))
         y2.fill_(float("nan"))
+        y3.fill_(float("nan"))
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), want) and np.array_equal(y2.cpu().numpy(), want2)
+        assert np.array_equal(y3.cpu().numpy(), want3)
         sellcs.sell_spmv(hs, x, y2)  # eager work between replays
+        sellcs.sell_spmv(hw, x, y3)
         torch.cuda.synchronize()
 
 
