@@ -50,6 +50,17 @@ __device__ int block_compact(int n, F flag, W write, int *tmp) {
   return total;
 }
 
+// Run starts (first set bit of each run of set bits) and run ends (last set
+// bit) of word w of a bitmap of nw words.
+__device__ __forceinline__ uint32_t run_starts(const uint32_t *bm, int w) {
+  const uint32_t x = bm[w], prev = w > 0 ? bm[w - 1] >> 31 : 0u;
+  return x & ~((x << 1) | prev);
+}
+__device__ __forceinline__ uint32_t run_ends(const uint32_t *bm, int w, int nw) {
+  const uint32_t x = bm[w], next = w + 1 < nw ? (bm[w + 1] & 1u) << 31 : 0u;
+  return x & ~((x >> 1) | next);
+}
+
 // One workgroup per group of kXwChunks chunks.
 // PASS 0: segment count per group into nseg[g] (and nseg[ngroups] = 0 for
 //         the scan), the largest window into *maxwin and the most segments
@@ -57,6 +68,13 @@ __device__ int block_compact(int n, F flag, W write, int *tmp) {
 //         kXwMaxSlots slots.
 // PASS 1: the segments, at 3 * segoff[g], and the window position of every
 //         slot of the group.
+// Groups whose columns span at most 32 * kXwMaxSlots values use a bitmap of
+// the span in LDS (distinct columns in order, their ranks by popcount, runs
+// from the edges of the set bits: linear in the slots and the span); the
+// others sort their column indices. Column 0, which every padding slot
+// holds, is kept out of the span: it becomes a window element and a run of
+// its own in front, unless column 1 is present (then the span starts at 0).
+// Both ways give the same window, runs and positions.
 template <int PASS>
 __global__ void __launch_bounds__(kXwBlock) k_xw_groups(const int32_t *__restrict__ col, const int64_t *__restrict__ cs,
                                                         int64_t nchunks, int64_t ngroups, int64_t *__restrict__ nseg,
@@ -66,6 +84,8 @@ __global__ void __launch_bounds__(kXwBlock) k_xw_groups(const int32_t *__restric
   __shared__ int32_t keys[kXwMaxSlots];
   __shared__ int32_t uk[kXwMaxSlots];
   __shared__ int tmp[kXwBlock];
+  __shared__ int32_t startb[kXwMaxSeg];
+  __shared__ int red[3];
   const int64_t g = blockIdx.x;
   const int tid = threadIdx.x;
   if (PASS == 0 && g == 0 && tid == 0) nseg[ngroups] = 0;
@@ -80,6 +100,129 @@ __global__ void __launch_bounds__(kXwBlock) k_xw_groups(const int32_t *__restric
     return;
   }
   const int n = (int)(se - sb);
+
+  // column range of the group, column 0 apart
+  if (tid == 0) {
+    red[0] = 0x7fffffff;
+    red[1] = -1;
+    red[2] = 0;
+  }
+  __syncthreads();
+  {
+    int lo = 0x7fffffff, hi = -1, z = 0;
+    for (int i = tid; i < n; i += kXwBlock) {
+      const int32_t c = col[sb + i];
+      if (c == 0) z = 1;
+      else {
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+      }
+    }
+    if (hi >= 0) {
+      atomicMin(&red[0], lo);
+      atomicMax(&red[1], hi);
+    }
+    if (z) atomicOr(&red[2], 1);
+  }
+  __syncthreads();
+  int lo = red[0], hi = red[1];
+  const bool has0 = red[2] != 0;
+  if (hi < 0) lo = hi = 0;        // column 0 only, or no slot
+  else if (has0 && lo <= 1) lo = 0;  // column 0 starts the first run
+  const int extra = has0 && lo > 0 ? 1 : 0;  // column 0 in front, a run of its own
+  const int64_t span = (int64_t)hi - lo + 1;
+  if (n > 0 && span <= 32 * (int64_t)kXwMaxSlots) {
+    uint32_t *bm = reinterpret_cast<uint32_t *>(keys);
+    int32_t *wpre = uk;  // distinct columns in the words before w
+    const int nw = (int)((span + 31) / 32);
+    for (int w = tid; w < nw; w += kXwBlock) bm[w] = 0u;
+    __syncthreads();
+    for (int i = tid; i < n; i += kXwBlock) {
+      const int32_t c = col[sb + i];
+      if (c != 0 || !extra) {
+        const int b = c - lo;
+        atomicOr(&bm[b >> 5], 1u << (b & 31));
+      }
+    }
+    __syncthreads();
+    const int per = (nw + kXwBlock - 1) / kXwBlock;
+    const int w0 = tid * per < nw ? tid * per : nw;
+    const int w1 = w0 + per < nw ? w0 + per : nw;
+    int cnt = 0, runs = 0;
+    for (int w = w0; w < w1; ++w) {
+      cnt += __popc(bm[w]);
+      runs += __popc(run_starts(bm, w));
+    }
+    int tot_cnt = 0, tot_runs = 0;
+    const int pc = block_exclusive_scan(cnt, tmp, &tot_cnt);
+    const int pr = block_exclusive_scan(runs, tmp, &tot_runs);
+    {
+      int acc = pc;
+      for (int w = w0; w < w1; ++w) {
+        wpre[w] = acc;
+        acc += __popc(bm[w]);
+      }
+    }
+    const int nuniq = tot_cnt + extra, ns = tot_runs + extra;
+    if (PASS == 0) {
+      if (tid == 0) {
+        nseg[g] = ns;
+        atomicMax(maxwin, nuniq);
+        atomicMax(maxseg, ns);
+      }
+      return;
+    }
+    if (ns > kXwMaxSeg) return;  // refused by the caller after the count pass
+    __syncthreads();             // wpre complete
+    int32_t *out = seg + 3 * segoff[g];
+    if (extra && tid == 0) {
+      out[0] = 0;
+      out[1] = 0;
+      out[2] = 1;
+    }
+    // run starts: first column and window position of each run
+    int k = extra + pr;
+    for (int w = w0; w < w1; ++w) {
+      uint32_t st = run_starts(bm, w);
+      while (st) {
+        const int b = __ffs(st) - 1;
+        st &= st - 1;
+        const int bit = w * 32 + b;
+        startb[k] = bit;
+        out[3 * k] = lo + bit;
+        out[3 * k + 1] = extra + wpre[w] + __popc(bm[w] & ((1u << b) - 1u));
+        ++k;
+      }
+    }
+    __syncthreads();  // startb complete
+    // run ends: the run that ends at bit e is the last one started at or
+    // before e
+    int before = pr;
+    for (int w = w0; w < w1; ++w) {
+      const uint32_t st = run_starts(bm, w);
+      uint32_t en = run_ends(bm, w, nw);
+      while (en) {
+        const int b = __ffs(en) - 1;
+        en &= en - 1;
+        const uint32_t upto = b == 31 ? 0xffffffffu : (2u << b) - 1u;
+        const int r = extra + before + __popc(st & upto) - 1;
+        out[3 * r + 2] = w * 32 + b - startb[r] + 1;
+      }
+      before += __popc(st);
+    }
+    // window position of every slot
+    for (int i = tid; i < n; i += kXwBlock) {
+      const int32_t c = col[sb + i];
+      int p = 0;
+      if (c != 0 || !extra) {
+        const int b = c - lo;
+        p = extra + wpre[b >> 5] + __popc(bm[b >> 5] & ((1u << (b & 31)) - 1u));
+      }
+      lcol[sb + i] = (uint16_t)p;
+    }
+    return;
+  }
+
   int P = 1;
   while (P < n) P <<= 1;
   for (int i = tid; i < P; i += kXwBlock) keys[i] = i < n ? col[sb + i] : 0x7fffffff;
