@@ -683,6 +683,125 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   }
 }
 
+// Block form for k = 16 * KV right-hand sides (KV = 2, 4): 16 lanes share
+// a row, lane q holding right-hand sides q*KV .. q*KV+KV-1, so the k values
+// of one row of X (one or two full lines) are read by one access of 16 lanes
+// and a wave covers 4 rows per access. Work units and the partial-sum layout
+// are those of k_spmmv with a single pass of width k; each unit (rpw rows of
+// a chunk) is shared by rpw/16 waves of 16 rows each (4 rows per lane
+// group), which walk the unit's chunk columns with U columns in flight; each
+// slot is read once. Per row the products are added in column order, as in
+// k_spmmv.
+template <int C, int KV>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) {
+  constexpr int RPW = C < 64 ? C : 64;
+  constexpr int WPC = C > 64 ? C / 64 : 1;
+  constexpr int SUB = RPW / 16;          // waves per unit
+  constexpr int RB = 4;                  // rows of a lane group
+  constexpr int U = KV >= 4 ? 1 : 2;     // chunk columns in flight
+  static_assert(RPW % 16 == 0, "blocks of 16 rows");
+  using VecT = typename DVec<KV>::type;
+
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t w = wv / SUB;
+  const int rb = (int)(wv - w * SUB) * 16;  // first row of this wave within the unit
+  if (w >= a.nwork) return;
+  int32_t item, seg = 0, nseg = 1;
+  int64_t poff = 0;
+  if (a.units) {
+    const Unit u = a.units[w];
+    item = u.item;
+    seg = u.seg;
+    nseg = u.nseg;
+    if (nseg > 1) poff = a.splits[u.sid].poff;
+  } else {
+    item = (int32_t)w;
+  }
+  const int k = a.k;  // 16 * KV
+  const int gq = lane >> 4, v0 = (lane & 15) * KV;
+  const int64_t chunk = item / WPC;
+  const int h = item - (int)(chunk * WPC);
+  const int64_t base = a.cs[chunk];
+  const int cl = a.cl[chunk];
+  int jb = 0, je = cl;
+  if (nseg > 1) {
+    jb = seg * a.seg_cols;
+    je = jb + a.seg_cols < cl ? jb + a.seg_cols : cl;
+  }
+  const int32_t *colc = a.col + base + h * RPW + rb + gq;
+  const double *valc = static_cast<const double *>(a.val) + base + h * RPW + rb + gq;
+  const double *X = static_cast<const double *>(a.x);
+  double *Y = static_cast<double *>(a.y);
+
+  double acc[RB][KV];
+#pragma unroll
+  for (int m = 0; m < RB; ++m)
+#pragma unroll
+    for (int v = 0; v < KV; ++v) acc[m][v] = 0.0;
+  int j = jb;
+  for (; j + U <= je; j += U) {
+    int32_t ci[U][RB];
+    double vv[U][RB];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < RB; ++m) {
+        const int64_t o = (int64_t)(j + u) * C + 4 * m;
+        ci[u][m] = ld_col(colc + o);
+        vv[u][m] = ld_val(valc + o);
+      }
+    // padding slots hold value 0: their rows skip the gather
+    VecT xg[U][RB];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < RB; ++m)
+        xg[u][m] = vv[u][m] != 0.0 ? *reinterpret_cast<const VecT *>(X + (int64_t)ci[u][m] * k + v0) : VecT{};
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < RB; ++m)
+#pragma unroll
+        for (int v = 0; v < KV; ++v) acc[m][v] = __builtin_fma(vv[u][m], vget<KV>(xg[u][m], v), acc[m][v]);
+  }
+  for (; j < je; ++j) {
+    int32_t ci[RB];
+    double vv[RB];
+#pragma unroll
+    for (int m = 0; m < RB; ++m) {
+      const int64_t o = (int64_t)j * C + 4 * m;
+      ci[m] = ld_col(colc + o);
+      vv[m] = ld_val(valc + o);
+    }
+#pragma unroll
+    for (int m = 0; m < RB; ++m)
+      if (vv[m] != 0.0) {
+        const VecT xg = *reinterpret_cast<const VecT *>(X + (int64_t)ci[m] * k + v0);
+#pragma unroll
+        for (int v = 0; v < KV; ++v) acc[m][v] = __builtin_fma(vv[m], vget<KV>(xg, v), acc[m][v]);
+      }
+  }
+#pragma unroll
+  for (int m = 0; m < RB; ++m) {
+    const int rl = rb + gq + 4 * m;
+    VecT o;
+    __builtin_memcpy(&o, acc[m], sizeof(o));
+    if (nseg == 1) {
+      const int64_t p = chunk * C + h * RPW + rl;
+      if (p < a.nrows) {
+        const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
+        __builtin_nontemporal_store(o, reinterpret_cast<VecT *>(Y + row * k + v0));
+      }
+    } else {
+      // partial[(poff + seg*RPW + rl)*k + v]: the layout of k_spmmv with one
+      // pass of width k
+      double *mine = static_cast<double *>(a.partial) + ((poff + (int64_t)seg * RPW + rl) * k + v0);
+      *reinterpret_cast<VecT *>(mine) = o;
+    }
+  }
+}
+
 // Block form: add the segment sums of split row slices. Block (w, tile):
 // split slice w, pass tile; one thread per (row, right-hand side) of the
 // slice (RPW * KT = 64 * KV threads), the segment sums added in segment

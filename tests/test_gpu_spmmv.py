@@ -95,3 +95,40 @@ def test_spmmv_misaligned_block():
     sellcs.sell_spmmv(h, Xv, Yv)
     torch.cuda.synchronize()
     check(A, Yv.cpu().numpy(), X)
+
+
+@pytest.mark.parametrize("k", [32, 64])
+@pytest.mark.parametrize("C,sigma,seg", [(16, 1, 64), (32, 30_000, 64), (64, 1, -1), (128, 1000, 32)])
+def test_spmmv_rows_kernel_equals_pass_kernel(k, C, sigma, seg):
+    """k = 32 and 64 with the automatic pass width run the 16-lanes-per-row
+    kernel; an explicit k-tile runs the pass kernel. Both add each row's
+    products in column order: equal bit for bit, and within the oracle's
+    bound (split rows included)."""
+    A = synth.powerlaw(30_000, seed=51)
+    X = synth.block_vector(A.ncols, k, seed=52)
+    h_rows = build(A, C, sigma, seg_cols=seg, kmax=64)
+    h_pass = build(A, C, sigma, seg_cols=seg, kmax=64, ktile=16)
+    say("spmmv rows k", k, "C", C, "sigma", sigma, "nsplit", h_rows.info["nsplit"])
+    Y_rows, Y_pass = run_spmmv(h_rows, X), run_spmmv(h_pass, X)
+    check(A, Y_rows, X)
+    assert np.array_equal(Y_rows, Y_pass)
+
+
+def test_spmmv_rows_kernel_misaligned_falls_back():
+    """X and Y 8 bytes off a 16-byte boundary at k = 32: the pass kernel
+    runs (narrower gathers) and the result is unchanged."""
+    import torch
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(20_000, seed=53)
+    k = 32
+    X = synth.block_vector(A.ncols, k, seed=54)
+    h = build(A, 32, A.nrows)
+    Xb = torch.zeros(A.ncols * k + 1, dtype=torch.float64, device="cuda")
+    Xb[1:] = torch.from_numpy(X.ravel()).cuda()
+    Yb = torch.zeros(A.nrows * k + 1, dtype=torch.float64, device="cuda")
+    Xv, Yv = Xb[1:].view(A.ncols, k), Yb[1:].view(A.nrows, k)
+    sellcs.sell_spmmv(h, Xv, Yv)
+    torch.cuda.synchronize()
+    Y = Yv.cpu().numpy()
+    check(A, Y, X)
+    assert np.array_equal(Y, run_spmmv(h, X))
