@@ -502,6 +502,7 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   return SELL_OK;
 }
 
+
 namespace {
 
 // Right-hand sides per lane (KV) for the block kernel: a power of two <= 8
@@ -528,21 +529,27 @@ extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t
   if (k == 1) return sell_spmv(h, X, Y, stream);
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: C must be >= 8 for k > 1");
   if (h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k exceeds the kmax given at build");
-  // k = 32 or 64 with the automatic pass width: 16 lanes per row, each row
-  // of X read whole by one access, one pass (X and Y aligned to the k/16
-  // doubles of a lane). Measured on the power-law 1M matrix: k = 32 at
-  // sigma = n 863 -> 997 GF/s, k = 64 915 -> 1015 (sigma = 1024: 421 -> 542);
-  // at k = 16 the two-lanes-per-row kernel stays faster (759 vs 731 at
-  // sigma = n, 384 vs 247 on the padding-heavy sigma = 1024 layout, whose
-  // matrix stream the 16-lane rows read less efficiently).
-  if (h->ktile == 0 && (k == 32 || k == 64) && h->C >= 16 &&
-      ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % (sizeof(double) * (k / 16))) == 0) {
-    sell::SpmvArgs a = args_of(h, X, Y);
-    a.k = k;
-    a.kt = k;
-    hipError_t e = sell::launch_spmmv_rows(h->C, k / 16, a, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail("sell_spmmv launch", e);
-    return SELL_OK;
+  // With the automatic pass width, k = 16, 32 and 64 run in one pass with
+  // LPR lanes per row: each row of X is read whole by one access (X and Y
+  // aligned to the k/LPR doubles of a lane). More lanes per row suit dense
+  // layouts, fewer (or the pass kernel) padding-heavy ones, whose matrix
+  // stream the lanes of a row read through broadcasts. Measured on the
+  // power-law 1M matrix at beta = 0.98 (sigma = n) / 0.14 (sigma = 1024),
+  // GF/s: k = 16 LPR 8 843 / 366, pass kernel 756 / 385; k = 32 LPR 16 997 /
+  // 410, LPR 8 835 / 477, pass kernel 862 / 402; k = 64 LPR 16 1013 / 543,
+  // pass kernel 913 / 421; k = 8 LPR 8 457 / 191, pass kernel 461 / 256.
+  {
+    const bool dense = h->beta >= 0.5;
+    const int lpr = k == 64 ? 16 : k == 32 ? (dense ? 16 : 8) : (k == 16 && dense) ? 8 : 0;
+    if (h->ktile == 0 && lpr > 0 && h->C >= 16 &&
+        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % (sizeof(double) * (k / lpr))) == 0) {
+      sell::SpmvArgs a = args_of(h, X, Y);
+      a.k = k;
+      a.kt = k;
+      hipError_t e = sell::launch_spmmv_rows(h->C, lpr, a, static_cast<hipStream_t>(stream));
+      if (e != hipSuccess) return hip_fail("sell_spmmv launch", e);
+      return SELL_OK;
+    }
   }
   int kv = choose_kv(h, k, h->ktile);
   // the gathers of KV contiguous right-hand sides and the stores of a lane's

@@ -84,22 +84,24 @@ hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmmv_rows(int C, int KV, const SpmvArgs &a, hipStream_t s) {
+hipError_t launch_spmmv_rows(int C, int LPR, const SpmvArgs &a, hipStream_t s) {
   if (a.nwork <= 0 || a.k <= 0) return hipSuccess;
   const int rpw = C < 64 ? C : 64;
   const int64_t waves = a.nwork * (rpw / 16);  // 16 rows per wave
   const unsigned nb = (unsigned)((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
   const unsigned ncomb = (unsigned)std::min(512, rpw * a.k);  // threads per combined slice
-#define SELL_L(CC, KK)                                                                                       \
-  if (C == CC && KV == KK) {                                                                                \
-    hipLaunchKernelGGL((dev::k_spmmv_rows<CC, KK>), dim3(nb), dim3(64 * dev::kWavesPerBlock), 0, s, a);    \
+  const int KV = a.k / LPR;
+#define SELL_L(CC, LL, KK)                                                                                   \
+  if (C == CC && LPR == LL && KV == KK) {                                                                   \
+    hipLaunchKernelGGL((dev::k_spmmv_rows<CC, LL, KK>), dim3(nb), dim3(64 * dev::kWavesPerBlock), 0, s, a); \
     hipError_t e_ = hipGetLastError();                                                                      \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                       \
     hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, 1), dim3(ncomb), 0, s, a);       \
     return hipGetLastError();                                                                               \
   }
-  SELL_L(16, 2) SELL_L(16, 4) SELL_L(32, 2) SELL_L(32, 4)
-  SELL_L(64, 2) SELL_L(64, 4) SELL_L(128, 2) SELL_L(128, 4)
+#define SELL_LC(LL, KK) SELL_L(16, LL, KK) SELL_L(32, LL, KK) SELL_L(64, LL, KK) SELL_L(128, LL, KK)
+  SELL_LC(8, 2) SELL_LC(8, 4) SELL_LC(16, 2) SELL_LC(16, 4)
+#undef SELL_LC
 #undef SELL_L
   return hipErrorInvalidValue;
 }

@@ -683,21 +683,21 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   }
 }
 
-// Block form for k = 16 * KV right-hand sides (KV = 2, 4): 16 lanes share
-// a row, lane q holding right-hand sides q*KV .. q*KV+KV-1, so the k values
-// of one row of X (one or two full lines) are read by one access of 16 lanes
-// and a wave covers 4 rows per access. Work units and the partial-sum layout
-// are those of k_spmmv with a single pass of width k; each unit (rpw rows of
-// a chunk) is shared by rpw/16 waves of 16 rows each (4 rows per lane
-// group), which walk the unit's chunk columns with U columns in flight; each
-// slot is read once. Per row the products are added in column order, as in
-// k_spmmv.
-template <int C, int KV>
+// Block form for k = LPR * KV right-hand sides: LPR lanes share a row (8 or
+// 16), lane q of a row holding right-hand sides q*KV .. q*KV+KV-1, so the k
+// values of one row of X are read by one access of LPR lanes and a wave
+// covers 64/LPR rows per access. Work units and the partial-sum layout are
+// those of k_spmmv with a single pass of width k; each unit (rpw rows of a
+// chunk) is shared by rpw/16 waves of 16 rows each, which walk the unit's
+// chunk columns with U columns in flight; each slot is read once. Per row
+// the products are added in column order, as in k_spmmv.
+template <int C, int LPR, int KV>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) {
   constexpr int RPW = C < 64 ? C : 64;
   constexpr int WPC = C > 64 ? C / 64 : 1;
   constexpr int SUB = RPW / 16;          // waves per unit
-  constexpr int RB = 4;                  // rows of a lane group
+  constexpr int RPA = 64 / LPR;          // rows per access
+  constexpr int RB = 16 / RPA;           // accesses (rows of a lane group) per wave
   constexpr int U = KV >= 4 ? 1 : 2;     // chunk columns in flight
   static_assert(RPW % 16 == 0, "blocks of 16 rows");
   using VecT = typename DVec<KV>::type;
@@ -718,8 +718,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   } else {
     item = (int32_t)w;
   }
-  const int k = a.k;  // 16 * KV
-  const int gq = lane >> 4, v0 = (lane & 15) * KV;
+  const int k = a.k;  // LPR * KV
+  const int gq = lane / LPR, v0 = (lane % LPR) * KV;
   const int64_t chunk = item / WPC;
   const int h = item - (int)(chunk * WPC);
   const int64_t base = a.cs[chunk];
@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int m = 0; m < RB; ++m) {
-        const int64_t o = (int64_t)(j + u) * C + 4 * m;
+        const int64_t o = (int64_t)(j + u) * C + RPA * m;
         ci[u][m] = ld_col(colc + o);
         vv[u][m] = ld_val(valc + o);
       }
@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
     double vv[RB];
 #pragma unroll
     for (int m = 0; m < RB; ++m) {
-      const int64_t o = (int64_t)j * C + 4 * m;
+      const int64_t o = (int64_t)j * C + RPA * m;
       ci[m] = ld_col(colc + o);
       vv[m] = ld_val(valc + o);
     }
@@ -784,7 +784,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   }
 #pragma unroll
   for (int m = 0; m < RB; ++m) {
-    const int rl = rb + gq + 4 * m;
+    const int rl = rb + gq + RPA * m;
     VecT o;
     __builtin_memcpy(&o, acc[m], sizeof(o));
     if (nseg == 1) {
