@@ -53,6 +53,7 @@ int64_t next_pow2(int64_t v) {
 
 struct DeviceInfo {
   int cus = 256;
+  size_t lds_per_block = 64 << 10;  // shared memory one workgroup may use
 };
 
 DeviceInfo device_info() {
@@ -61,8 +62,16 @@ DeviceInfo device_info() {
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) d.cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      d.lds_per_block = (size_t)v;
   }
   return d;
+}
+
+// Dynamic LDS of the x-window product: the window, then the segment table
+// with room for one entry per thread.
+size_t xw_lds_bytes(int64_t maxwin, int64_t maxseg, size_t xsz) {
+  return (((size_t)maxwin * xsz + 7) & ~(size_t)7) + 8 * (size_t)std::max<int64_t>(maxseg, 64 * sell::kXwChunks);
 }
 
 // Device memory through the caller's allocator or hipMalloc.
@@ -411,11 +420,12 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
       SELL_HIP(hipStreamSynchronize(s));
       const size_t xsz = h->xdt == SELL_F64 ? 8 : 4;
       const size_t budget = o.xwindow == 1 ? (size_t)64 << 10 : (size_t)16 << 10;
-      if (xs.flags || (size_t)xs.maxwin * xsz > budget || xs.maxseg > sell::kXwMaxSeg) {
+      if (xs.flags || (size_t)xs.maxwin * xsz > budget || xs.maxseg > sell::kXwMaxSeg ||
+          xw_lds_bytes(xs.maxwin, xs.maxseg, xsz) > di.lds_per_block) {
         if (o.xwindow == 1)
           return fail(SELL_ERR_UNSUPPORTED,
-                      "sell_build: x window too large (more than 8192 slots or 1024 column runs per group, or "
-                      "window over 64 KiB)");
+                      "sell_build: x window too large (more than 8192 slots or 1024 column runs per group, "
+                      "window over 64 KiB, or more LDS than a workgroup may use)");
       } else {
         h->xsegoff = static_cast<int64_t *>(owned_alloc(h.get(), mem, sizeof(int64_t) * (size_t)(ngroups + 1)));
         h->xseg = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * 3 * (size_t)xs.nseg));
@@ -491,9 +501,7 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   hipError_t e;
   if (h->lcol) {  // x windows staged in LDS
     const sell::XwArgs w{h->lcol, h->xsegoff, h->xseg, h->xwin_max};
-    // window, then the segment table with room for one entry per thread
-    const size_t lds = (((size_t)h->xwin_max * (h->xdt == SELL_F64 ? 8 : 4) + 7) & ~(size_t)7) +
-                       8 * (size_t)std::max(h->xseg_max, 64 * sell::kXwChunks);
+    const size_t lds = xw_lds_bytes(h->xwin_max, h->xseg_max, h->xdt == SELL_F64 ? 8 : 4);
     e = sell::launch_spmv_xw(h->combo, h->C, h->g.V, h->unroll / h->g.V, a, w, lds, static_cast<hipStream_t>(stream));
   } else {
     e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a, static_cast<hipStream_t>(stream));
