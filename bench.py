@@ -188,8 +188,8 @@ def run_forms(args, probes) -> dict:
     r, c, v = to_dev(A)
     spmmv = {}
     for C, sg in ((32, 1024), (32, A.nrows)):
-        h = sellcs.sell_build(r, c, v, A.ncols, C, sg)
-        for k in (1, 4, 8, 16, 32):
+        h = sellcs.sell_build(r, c, v, A.ncols, C, sg, kmax=64)
+        for k in (1, 4, 8, 16, 32, 64):
             X = torch.from_numpy(synth.block_vector(A.ncols, k)).cuda()
             Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
             t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
