@@ -94,11 +94,15 @@ def test_random_configuration(case):
         check_fp64_chain(A, h, C, y, x)
         assert np.array_equal(spmv_gpu(h, x).view(np.uint64), y.view(np.uint64))
         if C >= 8 and A.nrows > 0:
-            k = int(rng.choice([2, 3, 8, 16, 32, 64]))
+            k = int(rng.choice([2, 3, 8, 16, 32, 40, 64, 100]))
             X = synth.block_vector(A.ncols, k, seed=600 + case)
             Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
             Y = torch.full((A.nrows, k), float("nan"), dtype=torch.float64, device="cuda")
             say("  block form k", k)
+            if inf["nsplit"] > 0 and k > 64:  # beyond the kmax the partial sums were sized for
+                with pytest.raises(sellcs.SellError):
+                    sellcs.sell_spmmv(h, Xd, Y)
+                return
             sellcs.sell_spmmv(h, Xd, Y)
             torch.cuda.synchronize()
             Yc = Y.cpu().numpy()
