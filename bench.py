@@ -354,6 +354,38 @@ def sigma_sweep(args):
     print(json.dumps({"sigma_sweep": "powerlaw_2m", "C": 32, "n": A.nrows, "nnz": A.nnz, "rows": rows}))
 
 
+def block_pass(args):
+    """The block form on the power-law n = 1,000,000 matrix, SELL-32-n, k =
+    16, 32, 64 (the one-pass kernel with 8 or 16 lanes per row): time per
+    product, or under a counter run (--pmc-pass) exactly 3 products per k and
+    one copy probe for the counter calibration."""
+    import torch
+    import synth
+    from paper_1307_6209_amd import sellcs
+    A = synth.workload("powerlaw_1m")
+    r, c, v = to_dev(A)
+    h = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, kmax=64)
+    inf = h.info
+    rows = []
+    for k in (16, 32, 64):
+        X = torch.from_numpy(synth.block_vector(A.ncols, k)).cuda()
+        Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
+        if args.pmc_pass:
+            for _ in range(3):
+                sellcs.sell_spmmv(h, X, Y)
+            torch.cuda.synchronize()
+            t = float("nan")
+        else:
+            t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), 50, 5)
+        rows.append({"k": k, "us": round(t * 1e6, 2), "gfs": round(2.0 * A.nnz * k / t * 1e-9, 2)})
+        del X, Y
+    if args.pmc_pass:
+        sellcs.sell_probe_bandwidth(1, 1 << 30, 1)
+        torch.cuda.synchronize()
+    print(json.dumps({"block_pass": "powerlaw_1m", "C": 32, "sigma": A.nrows, "n": A.nrows, "nnz": A.nnz,
+                      "padded": inf["padded"], "beta": inf["beta"], "nsplit": inf["nsplit"], "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +398,8 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a few products and one copy probe")
     ap.add_argument("--sigma-sweep", action="store_true", help="SELL-32-sigma sweep on the power-law matrix")
+    ap.add_argument("--block-pass", action="store_true",
+                    help="block form k = 16, 32, 64 on the power-law 1M matrix (with --pmc-pass: for counters)")
     ap.add_argument("--probe-sweep", action="store_true",
                     help="random-gather probe over array sizes 1 MiB .. 4 GiB, and the read probe")
     args = ap.parse_args()
@@ -381,6 +415,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sigma_sweep:
         sigma_sweep(args)
+        return
+    if args.block_pass:
+        block_pass(args)
         return
     if args.probe_sweep:
         res = {"read_4gib_gbs": round(sellcs.sell_probe_bandwidth(0, 4 << 30, 10), 1)}
