@@ -698,7 +698,11 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   constexpr int SUB = RPW / 16;          // waves per unit
   constexpr int RPA = 64 / LPR;          // rows per access
   constexpr int RB = 16 / RPA;           // accesses (rows of a lane group) per wave
-  constexpr int U = KV >= 4 ? 1 : 2;     // chunk columns in flight
+  // chunk columns in flight: eight rows of X per lane for KV = 2, one
+  // column for KV = 4. Measured on the power-law 1M matrix: k = 16 (LPR 8)
+  // two columns 845 GF/s, four 1,055; k = 32 (LPR 16) two 997, four 925;
+  // k = 32 on the sigma = 1024 layout (LPR 8, KV 4) one 489, two 482.
+  constexpr int U = KV >= 4 ? 1 : 8 / RB;
   static_assert(RPW % 16 == 0, "blocks of 16 rows");
   using VecT = typename DVec<KV>::type;
 
