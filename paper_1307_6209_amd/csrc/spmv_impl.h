@@ -583,7 +583,12 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   constexpr int G = 64 / RPW;
   constexpr int WPC = C > 64 ? C / 64 : 1;
   constexpr int KT = G * KV;
-  constexpr int U = KV >= 4 ? 2 : 8 / KV;  // chunk columns in flight: more when each lane gathers little
+  // chunk columns in flight: eight (four for KV = 8). Measured on the
+  // power-law 1M matrix, GF/s at sigma = n / 1024, against 8 / KV (two for
+  // KV >= 4): k = 4 337 / 186 -> 375 / 199, k = 8 462 / 256 -> 684 / 292,
+  // k = 16 (KV = 8, sigma = 1024) 386 -> 406; sixteen for KV = 1 (k = 2, 3)
+  // was 7 % slower at sigma = 1024, 32 / KV slower throughout.
+  constexpr int U = KV >= 8 ? 4 : 8;
   using VecT = typename DVec<KV>::type;
 
   const int lane = threadIdx.x & 63;
