@@ -36,6 +36,16 @@ sys.path.insert(0, ROOT)
 METRIC = "spMVM GF/s + HBM GB/s vs 8 TB/s roofline; FP64 plain vs block-k/FP32/BF16"
 PEAK_HBM_GBS = 8000.0
 HEADLINE = dict(workload="stencil27_160", C=32, sigma=1)
+# The paper's own figures on its 2013 hardware (Sect. 5.2): context, not
+# targets. Model ceilings P_bar = b * beta / 6 with beta = 1 and the best
+# measured bandwidth of each device; the dense 8000^2 matrix; rail4284 on
+# the K20 with one and 32 threads per row.
+PAPER_CONTEXT = {
+    "note": "2013 hardware (Sandy Bridge Xeon E5-2680, Xeon Phi 5110P, Tesla K20c); context only",
+    "model_ceiling_gfs": {"snb": 7.2, "xeon_phi": 27.5, "k20": 25.2},
+    "dense_8000_gfs": {"snb": 7.3, "xeon_phi": 23.0, "k20": 17.0, "k20_16_threads_per_row": 31.0},
+    "rail4284_k20_gfs": {"1_thread_per_row": 0.5, "32_threads_per_row": 4.5},
+}
 
 
 def kernel_source_hash() -> str:
@@ -488,6 +498,7 @@ def main():
         "build_ms": round(build_s * 1e3, 2),
         "probes": probes,
         "kernel_source_hash": src_hash,
+        "paper_context": PAPER_CONTEXT,
     }
     if args.headline_only:
         h.close()
