@@ -185,8 +185,11 @@ sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream);
 
 /*
  * sell_spmmv -- Y = A X for k right-hand sides at once, asynchronous.
- * (Block form; the paper treats k = 1 only. Column v of Y equals sell_spmv
- * applied to column v of X.) FP64 handles only.
+ * (Block form; the paper treats k = 1 only. Column v of Y is mathematically
+ * sell_spmv applied to column v of X; the summation order differs, so the
+ * two agree within rounding, each within the FP64 bound of the oracle.)
+ * FP64 handles only. Each row's products are added in column order; the
+ * kernel (pass width, lanes per row) follows the ktile build option.
  *
  * X: device, row-major ncols x k (X[c*k + v]); Y: device, row-major
  * nrows x k, fully overwritten. k >= 1; on handles with split chunks k must
