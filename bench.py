@@ -260,6 +260,17 @@ def run_forms(args, probes) -> dict:
                                       "frac_of_gather_probe": round(8.0 * A.nnz / t * 1e-9 / probes["gather_16mib_gbs"],
                                                                     4)}
         h.close()
+    # the C x sigma grid of the irregular workload: beta and GF/s for C in
+    # {16, 32, 64, 128} and sigma in {1, C, 2^10, 2^14, n} (sigma = C gives the
+    # layout of sigma = 1)
+    grid = {}
+    for C in (16, 32, 64, 128):
+        for s in (1, C, 2**10, 2**14, A.nrows):
+            h = sellcs.sell_build(r, c, v, A.ncols, C, s)
+            t = time_calls(lambda: sellcs.sell_spmv(h, x, y), max(10, args.steps // 20), 3)
+            grid["C%d_sigma%d" % (C, s)] = {"beta": round(h.info["beta"], 4), "gfs": round(2.0 * A.nnz / t * 1e-9, 2)}
+            h.close()
+    pl["c_sigma_grid"] = grid
     # reduced-precision storage at the globally sorted layout; normwise error
     # against the FP64 product of the same rounded x
     xf = x.float()
