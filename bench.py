@@ -209,6 +209,15 @@ def run_forms(args, probes) -> dict:
                 spmmv["C%d_sigma%d_k%d_cold" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
         h.close()
     out["spmmv_powerlaw_1m_gfs"] = spmmv
+    # the block form autotuned over C, sigma and the pass width (0: the
+    # automatic choice, which includes the one-pass kernels)
+    tuned = {}
+    for k in (8, 32):
+        tk = sellcs.sell_autotune(r, c, v, A.ncols, k=k, C=(16, 32, 64), sigma=(1024, A.nrows), unroll=(8,),
+                                  ktile=(0, 8, 16, 32), reps=5)
+        tuned["k%d" % k] = {key: tk[key] for key in ("C", "sigma", "ktile", "candidates")}
+        tuned["k%d" % k]["gfs"] = round(tk["gflops"], 2)
+    out["spmmv_powerlaw_1m_autotuned"] = tuned
     del r, c, v
     # 64 uneven power-law matrices in one graph launch (sigma 1024, and
     # sigma = n_b, the fastest on these matrices in the sigma sweep)
