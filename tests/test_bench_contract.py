@@ -1,0 +1,31 @@
+"""The benchmark's contract on the host: one GPU only, and stored counter
+traffic used only for the kernel sources it was measured on."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_stored_traffic_only_for_matching_sources():
+    import bench
+    stored = json.load(open(os.path.join(ROOT, "profiles", "traffic_stencil27_160_fp64.json")))
+    assert bench.stored_traffic(stored["kernel_source_hash"]) == stored["hbm_bytes_per_launch"]
+    assert bench.stored_traffic("0" * 16) is None
+    assert len(bench.kernel_source_hash()) == 16
+
+
+def test_paper_context_is_context_only():
+    import bench
+    ctx = bench.PAPER_CONTEXT
+    assert set(ctx["model_ceiling_gfs"]) == {"snb", "xeon_phi", "k20"}
+    assert "context" in ctx["note"]
