@@ -81,6 +81,55 @@ def test_empty_rows_and_empty_matrix():
     assert np.array_equal(oracle.crs_spmv(Z, np.ones(3)), np.zeros(5))
 
 
+def dyadic_case(seed, n, m, max_len, vbits, xbits, vexp, xexp):
+    """Random matrix (empty rows, repeated and unsorted columns, n != m) whose
+    values are integers below 2^vbits times 2^vexp and x integers below
+    2^xbits times 2^xexp, signs mixed. Every product is an integer times
+    2^(vexp + xexp) of at most vbits + xbits bits."""
+    A = synth.random_crs(n, m, seed=seed, max_len=max_len, empty_frac=0.2, duplicates=True, unsorted=True)
+    iv = (synth.u64(seed, 31, A.nnz) % np.uint64(1 << vbits)).astype(np.int64)
+    iv[synth.u64(seed, 32, A.nnz) % np.uint64(2) == 1] *= -1
+    ix = (synth.u64(seed, 33, m) % np.uint64(1 << xbits)).astype(np.int64)
+    ix[synth.u64(seed, 34, m) % np.uint64(2) == 1] *= -1
+    A = synth.CRS(n, m, A.rpt, A.col, np.ldexp(iv.astype(np.float64), vexp))
+    return A, np.ldexp(ix.astype(np.float64), xexp), iv, ix
+
+
+@pytest.mark.parametrize("seed,vbits,xbits", [(1, 10, 10), (2, 26, 26), (3, 30, 28), (4, 31, 29)])
+def test_absmv_exact_rational(seed, vbits, xbits):
+    """(|A||x|)_i = sum over the row's stored entries of |a_ij| |x_col(j)|,
+    computed here in exact integers and rounded once to double by Python's
+    correctly rounded int -> float conversion. With at most 16 terms of at
+    most 60 bits every partial sum is an integer below 2^64 times 2^-18,
+    exact in the oracle's long double (64-bit significand), so
+    the oracle must return exactly this rounding (the larger cases need the
+    final rounding, which a mistaken sum would not reproduce)."""
+    A, x, iv, ix = dyadic_case(seed, 60, 45, 16, vbits, xbits, -7, -11)
+    got = oracle.crs_absmv(A, x)
+    for i in range(A.nrows):
+        s = sum(abs(int(iv[j])) * abs(int(ix[A.col[j]])) for j in range(int(A.rpt[i]), int(A.rpt[i + 1])))
+        want = math.ldexp(float(s), -18)  # int -> float rounds to nearest even; the scaling is exact
+        assert got[i] == want, (i, got[i], want)
+    assert np.all(got[A.row_lengths() == 0] == 0.0)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_absmv_two_sided_bound(seed):
+    """For arbitrary doubles: S_i (1 - g) <= (|A||x|)_i <= S_i (1 + g) with
+    S_i the exact rational sum, g = len_i 2^-63 + 2^-53 (long double sum,
+    then one rounding). A doubled, halved, sign-cancelled or mis-indexed sum
+    leaves this band."""
+    A = synth.random_crs(50, 35, seed=seed, max_len=30, duplicates=True, unsorted=True)
+    x = synth.uniform(35, seed, 4) * np.ldexp(1.0, (synth.u64(seed, 5, 35) % np.uint64(40)).astype(np.int64) - 20)
+    got = oracle.crs_absmv(A, x)
+    lens = A.row_lengths()
+    for i in range(A.nrows):
+        S = sum((abs(Fraction(float(A.val[j]))) * abs(Fraction(float(x[A.col[j]])))
+                 for j in range(int(A.rpt[i]), int(A.rpt[i + 1]))), Fraction(0))
+        g = Fraction(int(lens[i]) + 1, 2 ** 63) + Fraction(1, 2 ** 53)
+        assert S * (1 - g) <= Fraction(float(got[i])) <= S * (1 + g), i
+
+
 @pytest.mark.parametrize("m", [2, 5, 128])
 def test_laplacian_row_sums(m):
     """5-point Laplacian (diag 4, neighbours -1) times the ones vector:

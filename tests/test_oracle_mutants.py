@@ -1,7 +1,8 @@
 """Planted mistakes: copies of the oracle compiled with one plausible error
 each (reversed sort, dropped term, transposed slot index, short chunk
-maximum, truncating rounding, ...) must each fail at least one pin. The
-mistakes live only in temporary copies; the oracle itself is untouched."""
+maximum, truncating rounding, a wrong |A||x| scale, ...) must each fail at
+least one pin. The mistakes live only in temporary copies; the oracle itself
+is untouched."""
 import ctypes
 import os
 import subprocess
@@ -51,6 +52,26 @@ MUTANTS = {
                              lambda: sell_pins.test_symmetric_permutation_identity(100)]),
     "block_form_wrong_stride": ("(long double)X[(int64_t)col[j] * k + v];", "(long double)X[(int64_t)col[j] + v];",
                                 [lambda: crs_pins.test_block_form_columns_match_single_vector()]),
+    "absmv_no_fabs_x": ("s += fabsl((long double)val[j]) * fabsl((long double)x[col[j]]);",
+                        "s += fabsl((long double)val[j]) * ((long double)x[col[j]]);",
+                        [lambda: crs_pins.test_absmv_exact_rational(2, 26, 26),
+                         lambda: crs_pins.test_absmv_two_sided_bound(5)]),
+    "absmv_doubled": ("s += fabsl((long double)val[j]) * fabsl((long double)x[col[j]]);",
+                      "s += 2 * fabsl((long double)val[j]) * fabsl((long double)x[col[j]]);",
+                      [lambda: crs_pins.test_absmv_exact_rational(1, 10, 10),
+                       lambda: crs_pins.test_absmv_two_sided_bound(6)]),
+    "absmv_first_column": ("s += fabsl((long double)val[j]) * fabsl((long double)x[col[j]]);",
+                           "s += fabsl((long double)val[j]) * fabsl((long double)x[col[rpt[i]]]);",
+                           [lambda: crs_pins.test_absmv_exact_rational(3, 30, 28),
+                            lambda: crs_pins.test_absmv_two_sided_bound(5)]),
+    "f32_truncates": ("for (int64_t t = 0; t < count; ++t) out[t] = (float)in[t];",
+                      "for (int64_t t = 0; t < count; ++t) {\n    float f_ = (float)in[t];\n"
+                      "    if (fabs((double)f_) > fabs(in[t])) f_ = nextafterf(f_, 0.0f);\n    out[t] = f_;\n  }",
+                      [lambda: rnd_pins.test_f32_golden_cases()]),
+    "f32_flushes_subnormals": ("for (int64_t t = 0; t < count; ++t) out[t] = (float)in[t];",
+                               "for (int64_t t = 0; t < count; ++t)\n"
+                               "    out[t] = fabs(in[t]) < 0x1p-126 ? copysignf(0.0f, (float)in[t]) : (float)in[t];",
+                               [lambda: rnd_pins.test_f32_golden_cases()]),
     "zeta_wrong_mean": ("long double d = (long double)(rpt[i + 1] - rpt[i]) - mean;",
                         "long double d = (long double)(rpt[i + 1] - rpt[i]) - mean + 1;",
                         [lambda: sell_pins.test_zeta_closed_form()]),

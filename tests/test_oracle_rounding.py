@@ -72,3 +72,18 @@ def test_bf16_roundtrip_exact():
     again = oracle.round_bf16(v[finite])
     # +0 and -0 both map to themselves; every finite pattern is a fixed point
     assert np.array_equal(again, bits[finite])
+
+
+def test_f32_golden_cases():
+    """Binary32 rounding against encodings derived by hand (ties to even,
+    the overflow threshold, the subnormal range, signed zeros)."""
+    d = json.load(open(os.path.join(HERE, "golden", "f32_rounding.json")))
+    xs = np.array([float(c["x"]) if "inf" in c["x"] else float.fromhex(c["x"]) for c in d["cases"]])
+    got = oracle.round_f32(xs).view(np.uint32)
+    bad = [(c["x"], hex(int(g)), c["bits"]) for c, g in zip(d["cases"], got) if int(g) != int(c["bits"], 16)]
+    assert not bad
+
+
+def test_f32_nan_stays_nan():
+    got = oracle.round_f32(np.array([np.nan, -np.nan])).view(np.uint32)
+    assert np.all((got & 0x7F800000) == 0x7F800000) and np.all((got & 0x007FFFFF) != 0)
