@@ -133,6 +133,7 @@ typedef struct {
   int32_t xwindow;       /* 1 when sell_spmv stages x windows in LDS */
   int32_t xwindow_max;   /* largest window, in x elements */
   int64_t xsegments;     /* runs of consecutive columns over all windows */
+  int32_t xwindow_group_chunks; /* chunks that share one x window (a workgroup) */
 } sell_info_t;
 
 /*
@@ -194,6 +195,10 @@ sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream);
  * X: device, row-major ncols x k (X[c*k + v]); Y: device, row-major
  * nrows x k, fully overwritten. k >= 1; on handles with split chunks k must
  * not exceed the kmax given at build. Same overlap rule as sell_spmv.
+ * X must be finite: for k > 1 every slot holding value 0 -- padding and
+ * explicit zero entries alike -- skips its gather of X, so an Inf or NaN in
+ * a row of X that only zero slots name does not reach Y (0 * Inf would give
+ * NaN); k = 1 follows sell_spmv.
  */
 sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t k,
                        void *stream);
@@ -210,6 +215,26 @@ sell_status sell_info(sell_handle h, sell_info_t *info);
  */
 sell_status sell_export(sell_handle h, int32_t *perm, int32_t *cl, int64_t *cs,
                         int32_t *col, void *val);
+
+/*
+ * sell_export_xwindow -- copy the x-window tables of a handle built with the
+ * x window (sell_info_t.xwindow == 1) to host buffers (synchronous). Group g
+ * is chunks g*G .. g*G+G-1 (G = xwindow_group_chunks, the last group may be
+ * short); its window is the sorted list of the distinct column indices its
+ * slots hold (padding slots hold column 0), stored as runs of consecutive
+ * columns.
+ *   segoff: ngroups + 1 int64, ngroups = ceil(nchunks / G); the runs of group
+ *           g are segoff[g] .. segoff[g+1]-1.
+ *   seg:    3 * xsegments int32; run s is (first column, window position of
+ *           that column, length).
+ *   lcol:   padded uint16; the window position of the column of every slot
+ *           (slot order of sell_export's col).
+ * Any pointer may be NULL to skip that array. Errors: SELL_ERR_INVALID_ARG
+ * for a null handle, SELL_ERR_UNSUPPORTED when the handle has no x window.
+ * (An inspection call: the window is an addition of this library to the
+ * paper's layout, Sect. 3.3, which the paper's format does not hold.)
+ */
+sell_status sell_export_xwindow(sell_handle h, int64_t *segoff, int32_t *seg, uint16_t *lcol);
 
 /* sell_destroy -- release the handle and its device memory (synchronises
  * the device first). NULL is accepted. */

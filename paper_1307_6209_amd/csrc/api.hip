@@ -608,6 +608,7 @@ extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
   r.xwindow = h->lcol ? 1 : 0;
   r.xwindow_max = h->xwin_max;
   r.xsegments = h->nxseg;
+  r.xwindow_group_chunks = sell::kXwChunks;
   *info = r;
   return SELL_OK;
 }
@@ -625,6 +626,20 @@ extern "C" sell_status sell_export(sell_handle h, int32_t *perm, int32_t *cl, in
   if (col && h->padded > 0) SELL_HIP(hipMemcpy(col, h->col, sizeof(int32_t) * (size_t)h->padded, hipMemcpyDeviceToHost));
   if (val && h->padded > 0)
     SELL_HIP(hipMemcpy(val, h->val, dtype_size(h->vdt) * (size_t)h->padded, hipMemcpyDeviceToHost));
+  return SELL_OK;
+}
+
+extern "C" sell_status sell_export_xwindow(sell_handle h, int64_t *segoff, int32_t *seg, uint16_t *lcol) {
+  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_export_xwindow: null handle");
+  if (!h->lcol) return fail(SELL_ERR_UNSUPPORTED, "sell_export_xwindow: the handle has no x window");
+  SELL_HIP(hipDeviceSynchronize());
+  const int64_t ngroups = (h->nchunks + sell::kXwChunks - 1) / sell::kXwChunks;
+  if (segoff)
+    SELL_HIP(hipMemcpy(segoff, h->xsegoff, sizeof(int64_t) * (size_t)(ngroups + 1), hipMemcpyDeviceToHost));
+  if (seg && h->nxseg > 0)
+    SELL_HIP(hipMemcpy(seg, h->xseg, sizeof(int32_t) * 3 * (size_t)h->nxseg, hipMemcpyDeviceToHost));
+  if (lcol && h->padded > 0)
+    SELL_HIP(hipMemcpy(lcol, h->lcol, sizeof(uint16_t) * (size_t)h->padded, hipMemcpyDeviceToHost));
   return SELL_OK;
 }
 

@@ -51,7 +51,7 @@ class SellInfo(ctypes.Structure):
                 ("val_dtype", ctypes.c_int), ("x_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int),
                 ("lanes_per_row", c_i32), ("unroll", c_i32), ("vec", c_i32), ("seg_cols", c_i32), ("nunits", c_i64),
                 ("nsplit", c_i64), ("has_perm", c_i32), ("permuted_columns", c_i32), ("device_bytes", c_i64),
-                ("xwindow", c_i32), ("xwindow_max", c_i32), ("xsegments", c_i64)]
+                ("xwindow", c_i32), ("xwindow_max", c_i32), ("xsegments", c_i64), ("xwindow_group_chunks", c_i32)]
 
 
 class SellTuneSpace(ctypes.Structure):
@@ -82,6 +82,7 @@ SIGNATURES = {
     "sell_spmmv": (ctypes.c_int, [c_p, c_p, c_p, c_i32, c_p]),
     "sell_info": (ctypes.c_int, [c_p, ctypes.POINTER(SellInfo)]),
     "sell_export": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p, c_p]),
+    "sell_export_xwindow": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
     "sell_destroy": (ctypes.c_int, [c_p]),
     "sell_batch_create": (ctypes.c_int, [ctypes.POINTER(c_p), c_i32, ctypes.POINTER(c_p)]),
     "sell_batch_create_persistent": (ctypes.c_int, [ctypes.POINTER(c_p), c_i32, ctypes.POINTER(c_p)]),
@@ -307,6 +308,20 @@ def sell_export(h: SellMatrix, parts=("perm", "cl", "cs", "col", "val")) -> dict
     out = {k: np.empty(shapes[k][0], shapes[k][1]) for k in parts}
     p = lambda k: ctypes.c_void_p(out[k].ctypes.data) if k in out else None  # noqa: E731
     _check(lib().sell_export(h.handle, p("perm"), p("cl"), p("cs"), p("col"), p("val")), "sell_export")
+    return out
+
+
+def sell_export_xwindow(h: SellMatrix) -> dict:
+    """Host copies (numpy) of the x-window tables: segoff (ngroups + 1),
+    seg (xsegments x 3: first column, window position, length) and lcol
+    (window position of every slot)."""
+    inf = h.info
+    G = inf["xwindow_group_chunks"]
+    ngroups = (inf["nchunks"] + G - 1) // G
+    out = {"segoff": np.empty(ngroups + 1, np.int64), "seg": np.empty((inf["xsegments"], 3), np.int32),
+           "lcol": np.empty(inf["padded"], np.uint16), "group_chunks": G}
+    p = lambda k: ctypes.c_void_p(out[k].ctypes.data)  # noqa: E731
+    _check(lib().sell_export_xwindow(h.handle, p("segoff"), p("seg"), p("lcol")), "sell_export_xwindow")
     return out
 
 

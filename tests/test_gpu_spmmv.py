@@ -133,3 +133,27 @@ def test_spmmv_rows_kernel_misaligned_falls_back():
     Y = Yv.cpu().numpy()
     check(A, Y, X)
     assert np.array_equal(Y, run_spmmv(h, X))
+
+
+@pytest.mark.parametrize("k,ktile", [(4, 0), (16, 0), (32, 0), (64, 0), (32, 8)])
+@pytest.mark.parametrize("sigma", [1, 10**9])
+def test_spmmv_explicit_zero_entries(k, ktile, sigma):
+    """Explicit zero values (a quarter of the entries, whole rows among them)
+    with finite X: the block kernels skip the gather of every zero slot, and
+    the result still matches the oracle, where those terms add exactly 0.
+    Both the pass kernel and the one-pass row kernels (k = 16, 32, 64 with
+    the automatic pass width), dense and padding-heavy layouts."""
+    A = synth.powerlaw(20_000, seed=47)
+    zero = (synth.u64(48, 1, A.nnz) % np.uint64(4)) == 0
+    lens = A.row_lengths()
+    zero |= np.repeat((synth.u64(48, 2, A.nrows) % np.uint64(10)) == 0, lens)  # whole rows of zeros
+    val = np.where(zero, 0.0, A.val)
+    B = synth.CRS(A.nrows, A.ncols, A.rpt, A.col, val)
+    X = synth.block_vector(B.ncols, k, seed=49)
+    h = build(B, 32, sigma, ktile=ktile, kmax=64)
+    say("explicit zeros k", k, "ktile", ktile, "sigma", sigma, "beta", round(h.info["beta"], 3),
+        "zero entries", int(zero.sum()))
+    Y = run_spmmv(h, X)
+    check(B, Y, X)
+    allzero = np.array([not np.any(~zero[A.rpt[i]:A.rpt[i + 1]]) for i in range(A.nrows)])
+    assert np.all(Y[allzero] == 0.0)

@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import assert_layout_equal, build, check_fp64, say, spmv_gpu
+from gpu_util import assert_layout_equal, build, check_fp64, check_reduced, say, spmv_gpu
+from xwindow_def import window_tables
 
 pytestmark = pytest.mark.gpu
 
@@ -68,6 +69,8 @@ def test_window_reduced_precision_bitwise(val_dtype, acc, C, vec):
     assert on.info["xwindow"] == 1 and on.info["vec"] == vec
     y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
     assert np.array_equal(y_on, y_off)
+    comp, norm = check_reduced(A, on, x, val_dtype, acc, C)
+    say("window", val_dtype, acc, "C", C, "vec", vec, "componentwise %.3g normwise %.3g" % (comp, norm))
 
 
 def test_window_default_slots_per_lane():
@@ -227,3 +230,67 @@ def test_window_largest_required(val_dtype, acc):
     assert np.array_equal(y_on, y_off)
     if val_dtype == "f64":
         check_fp64(A, y_on, x)
+
+
+def span_matrix():
+    """Three groups of four 32-row chunks over 600,000 columns. Group 0: rows
+    of one or two entries at columns 2..51 and 262,145 -- the span 2..262,145
+    is exactly 32 * 8192 values (the builder's bitmap), with column 0 from
+    padding kept apart in front. Group 1: columns 5..34 and 262,150, one value
+    more (the builder sorts). Group 2: columns 1, 3 and the row index, with
+    padding: column 0 joins the first run."""
+    rows = []
+    for i in range(384):
+        if i < 128:
+            c = [2 + i % 50] + ([262_145] if i % 2 == 0 else [])
+        elif i < 256:
+            c = [5 + i % 30] + ([262_150] if i % 3 == 0 else [])
+        else:
+            c = sorted({1, 3, i}) if i % 4 else [1]
+        rows.append(c)
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum([len(c) for c in rows], out=rpt[1:])
+    col = np.concatenate([np.array(c, np.int32) for c in rows])
+    return synth.CRS(len(rows), 600_000, rpt, col, synth.uniform(col.size, 88, 1))
+
+
+TABLE_CASES = [
+    ("stencil27_24_C32", lambda: synth.stencil27(24), 32, 1, 0),
+    ("stencil27_24_C16_vec2", lambda: synth.stencil27(24), 16, 64, 2),
+    ("lap5_96_C8", lambda: synth.lap5(96), 8, 1, 0),
+    ("banded_3000_C64", lambda: banded(3000, 7), 64, 4096, 1),
+    ("powerlaw_5000_C8", lambda: synth.powerlaw(5000, seed=12, lmax=100), 8, 1, 0),
+    ("powerlaw_5000_C16_sorted", lambda: synth.powerlaw(5000, seed=13, lmax=20), 16, 10**9, 1),
+    ("ragged_1000_C32", lambda: blocks_with_empty_runs(43), 32, 1, 0),
+    ("span_limit_C32", span_matrix, 32, 1, 0),
+]
+
+
+@pytest.mark.parametrize("name,make,C,sigma,vec", TABLE_CASES, ids=[c[0] for c in TABLE_CASES])
+def test_window_tables_match_definition(name, make, C, sigma, vec):
+    """The window tables the builder stores (run offsets per group, the runs,
+    the 16-bit position of every slot) against their plain definition --
+    sorted distinct columns of each group of chunks, position = rank -- taken
+    from the oracle's layout, for every group."""
+    from paper_1307_6209_amd import sellcs
+    A = make()
+    h = build(A, C, sigma, vec=vec, xwindow=1)
+    assert h.info["xwindow"] == 1
+    got = sellcs.sell_export_xwindow(h)
+    lay = oracle.sell_build(A, C, sigma)
+    segoff, seg, lcol = window_tables(lay["col"], lay["cs"], got["group_chunks"])
+    say("window tables", name, "groups", segoff.size - 1, "runs", seg.shape[0], "largest", h.info["xwindow_max"])
+    assert np.array_equal(got["segoff"], segoff)
+    assert np.array_equal(got["seg"].astype(np.int64), seg)
+    assert np.array_equal(got["lcol"].astype(np.int64), lcol)
+    assert h.info["xsegments"] == seg.shape[0]
+    assert h.info["xwindow_max"] == max(int(seg[a:b, 2].sum()) for a, b in zip(segoff[:-1], segoff[1:]))
+    check_fp64(A, spmv_gpu(h, synth.uniform(A.ncols, 38, 1)), synth.uniform(A.ncols, 38, 1))
+
+
+def test_window_tables_without_window_refused():
+    from paper_1307_6209_amd import sellcs
+    h = build(synth.stencil27(10), 32, 1, xwindow=-1)
+    with pytest.raises(sellcs.SellError) as e:
+        sellcs.sell_export_xwindow(h)
+    assert e.value.status == sellcs.SELL_ERR_UNSUPPORTED
