@@ -8,16 +8,22 @@ bracketed by device synchronisations and timed with HIP events on the stream
 the kernels run on. GF/s counts the useful 2 * nnz flops per product.
 
 Printed as one JSON line, with
-  roofline: algorithmic bytes of one product (padded matrix at 12 B per slot,
-            x and y once, chunk metadata) over the measured time per product,
-            against the 8 TB/s HBM peak; traffic = HBM bytes per product from
-            the hardware counters recorded under profiles/ when the kernel
-            sources are unchanged since, else null;
+  roofline: the method's algorithmic bytes of one product (padded matrix at
+            12 B per slot, x and y once, chunk metadata) over the measured
+            time per product, against the 8 TB/s HBM peak; beside them the
+            bytes the x-window format itself moves (10 B per slot and the
+            window tables) and their fraction; traffic = HBM bytes per
+            product from the hardware counters recorded under profiles/ when
+            the kernel sources are unchanged since, else null;
   cpu_baseline: the CPU oracle (CRS, double, OpenMP over rows) on the same
             matrix on the host cores;
-  forms:    FP32 / BF16 value storage, the block form (k right-hand sides) on
-            the power-law n = 1,000,000 matrix, the batched launch over 64
-            power-law matrices, and the power-law n = 2,000,000 matrix;
+  errors_vs_oracle: normwise and componentwise errors of the headline FP64
+            product and of every reduced-precision result against the
+            oracle (computed after all timing, in the CPU leg);
+  forms:    FP32 / BF16 value storage (x window and int32 indices), the
+            block form (k right-hand sides) on the power-law n = 1,000,000
+            matrix, the batched launch over 64 power-law matrices, and the
+            power-law n = 2,000,000 matrix;
   probes:   read-only and copy bandwidth (the paper's roofline b).
 """
 from __future__ import annotations
@@ -74,6 +80,11 @@ def to_dev(A):
     return (torch.from_numpy(A.rpt).cuda(), torch.from_numpy(A.col).cuda(), torch.from_numpy(A.val).cuda())
 
 
+def progress(*a):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
 def time_calls(fn, steps: int, warmup: int, repeats: int = 5):
     """Seconds per call of fn after `warmup` calls: `steps` back-to-back calls
     cut into `repeats` groups, each timed by its own events; the median group
@@ -123,6 +134,43 @@ def cpu_baseline(A, x, budget_s: float = 10.0, C: int = 32, sigma: int = 1) -> d
             "sell_build_ms": round(t_build * 1e3, 1), "sell_build_format": "SELL-%d-%d" % (C, sigma)}
 
 
+def errors_vs_oracle(y_head, checks, checks_x) -> dict:
+    """Errors of the benchmarked results against the oracle (long double
+    CRS product, rounded once): the FP64 headline product against A x, and
+    every reduced-precision result against A x^ (x^ = x rounded to binary32,
+    the input those forms multiply), as the normwise error
+    ||y - y_ref||_2 / ||y_ref||_2 and the componentwise
+    max_i |y_i - y_ref_i| / (|A||x^|)_i."""
+    import numpy as np
+    import oracle
+
+    def errs(y, yref, scale):
+        d = np.abs(y - yref)
+        return {"normwise": float("%.3g" % (np.linalg.norm(d) / max(np.linalg.norm(yref), 1e-300))),
+                "componentwise": float("%.3g" % np.max(d / np.where(scale > 0, scale, 1.0)))}
+
+    A, x = checks_x["stencil27_160"]
+    out = {"headline_fp64": errs(y_head, oracle.crs_spmv_hi(A, x), oracle.crs_absmv(A, x))}
+    out["headline_fp64"]["componentwise_bound"] = 1e-13
+    refs = {}
+    for wl, key, _vd, y in checks:
+        if wl not in refs:
+            A, x = checks_x[wl]
+            xr = oracle.round_f32(x).astype(np.float64)
+            refs[wl] = (oracle.crs_spmv_hi(A, xr), oracle.crs_absmv(A, xr))
+        yref, scale = refs[wl]
+        out.setdefault(wl, {})[key] = errs(y, yref, scale)
+    return out
+
+
+def cpu_baseline_leg(A, x, y_head, checks, checks_x) -> tuple:
+    """The part of the benchmark that runs the CPU oracle: its timing on the
+    host cores, and the errors of the benchmarked results against it (after
+    every timed region)."""
+    base = cpu_baseline(A, x, C=HEADLINE["C"], sigma=HEADLINE["sigma"])
+    return base, errors_vs_oracle(y_head, checks, checks_x)
+
+
 def graph_time(fn, launches: int, replays: int = 5) -> float:
     """Seconds per call of fn from a captured graph of `launches` calls,
     replayed back to back (launch overhead amortised)."""
@@ -148,13 +196,6 @@ def graph_time(fn, launches: int, replays: int = 5) -> float:
     return e0.elapsed_time(e1) * 1e-3 / (replays * launches)
 
 
-def normwise(y, yref) -> float:
-    """||y - yref||_2 / ||yref||_2 of two device vectors (in float64)."""
-    import torch
-    d = torch.linalg.vector_norm(y.double() - yref)
-    return float(d / torch.clamp(torch.linalg.vector_norm(yref), min=1e-300))
-
-
 def cold_time(fn, flush, reps: int = 21) -> float:
     """Median seconds of single calls of fn, each timed by its own events
     right after a read-modify-write of `flush` (1 GiB: evicts every L2 and
@@ -173,7 +214,7 @@ def cold_time(fn, flush, reps: int = 21) -> float:
     return ts[len(ts) // 2] * 1e-3
 
 
-def run_forms(args, probes) -> dict:
+def run_forms(args, probes, checks, checks_x) -> dict:
     import torch
     import numpy as np
     import synth
@@ -194,6 +235,7 @@ def run_forms(args, probes) -> dict:
     h.close()
     del r, c, v
     # block form on the power-law n = 1,000,000 matrix
+    progress("block form")
     A = synth.workload("powerlaw_1m")
     r, c, v = to_dev(A)
     spmmv = {}
@@ -221,6 +263,7 @@ def run_forms(args, probes) -> dict:
     del r, c, v
     # 64 uneven power-law matrices in one graph launch (sigma 1024, and
     # sigma = n_b, the fastest on these matrices in the sigma sweep)
+    progress("batched launch")
     mats = synth.batch_workload(64)
     devs = [to_dev(B) for B in mats]
     xs = [torch.from_numpy(synth.uniform(B.ncols, 5 + i)).cuda() for i, B in enumerate(mats)]
@@ -254,6 +297,7 @@ def run_forms(args, probes) -> dict:
                                 "sigma_counts": hist, "candidates": tb["candidates"]}
     del devs
     # power-law n = 2,000,000: plain and globally sorted
+    progress("power-law 2M")
     A = synth.workload("powerlaw_2m")
     r, c, v = to_dev(A)
     x = torch.from_numpy(synth.uniform(A.ncols)).cuda()
@@ -280,21 +324,19 @@ def run_forms(args, probes) -> dict:
             grid["C%d_sigma%d" % (C, s)] = {"beta": round(h.info["beta"], 4), "gfs": round(2.0 * A.nnz / t * 1e-9, 2)}
             h.close()
     pl["c_sigma_grid"] = grid
-    # reduced-precision storage at the globally sorted layout; normwise error
-    # against the FP64 product of the same rounded x
+    # reduced-precision storage at the globally sorted layout (int32 column
+    # indices: the uniform half of the columns leaves no x window); the
+    # results go to the oracle leg for their errors
     xf = x.float()
-    h = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows)
-    y64 = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
-    sellcs.sell_spmv(h, xf.double(), y64)
-    h.close()
     for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
         h = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, val_dtype=vd, acc_dtype=ad)
         yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
         t = time_calls(lambda: sellcs.sell_spmv(h, xf, yf), max(20, args.steps // 5), 5)
-        pl["C32_sigma%d_%s_val_%s_acc" % (A.nrows, vd, ad)] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2),
-                                                               "normwise_err_vs_fp64": float(
-                                                                   "%.3g" % normwise(yf, y64))}
+        key = "C32_sigma%d_%s_val_%s_acc" % (A.nrows, vd, ad)
+        pl[key] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "index": "int32" if h.info["xwindow"] == 0 else "uint16"}
+        checks.append(("powerlaw_2m", key, vd, yf.double().cpu().numpy()))
         h.close()
+    checks_x["powerlaw_2m"] = (A, x.cpu().numpy())
     hs_ = sellcs.sell_build(r, c, v, A.ncols, 32, A.nrows, permute_columns=True)
     xp = torch.empty_like(x)
     sellcs.sell_permute(hs_, x, xp)
@@ -307,6 +349,7 @@ def run_forms(args, probes) -> dict:
     out["powerlaw_2m"] = pl
     del r, c, v
     # few rows, long rows: dense 8000^2 and a rail4284-shaped matrix (Sect. 5.2)
+    progress("dense and rail-shaped")
     for name, Cs in (("dense_8000", (32, 128)), ("rail_like", (32, 128))):
         B = synth.workload(name)
         rr, cc, vv = to_dev(B)
@@ -485,10 +528,19 @@ def main():
 
     sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup, repeats=1)
     gfs = 2.0 * A.nnz / sec * 1e-9
+    torch.cuda.synchronize()
+    y_head = y.cpu().numpy()
+    # algorithmic bytes of the method (12 B per padded slot: FP64 value and
+    # int32 column index; x and y once; the permutation when sigma > 1; cl and
+    # cs per chunk) and the bytes the x-window format itself moves (2-byte
+    # window positions plus the window tables)
+    sizes_alg = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1)
+    alg = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes_alg)
     sizes = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1, xwindow=inf["xwindow"] == 1,
                             segments_per_chunk=inf["xsegments"] / max(1, inf["nchunks"]))
-    alg = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes)
+    moved = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes)
     achieved = alg / sec * 1e-9
+    achieved_moved = moved / sec * 1e-9
     src_hash = kernel_source_hash()
     traffic = stored_traffic(src_hash)
     nnzr = A.nnz / A.nrows
@@ -513,8 +565,20 @@ def main():
                    "values": "f64", "x": "f64", "y": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg},
-        "model": model_report(model, probes["read_gbs"], gfs, achieved, inf, A, sizes, traffic),
+                     "algorithmic_bytes_per_launch": alg,
+                     "algorithmic_bytes_basis": "12 B per padded slot (FP64 value + int32 index), x and y once, "
+                                                "12 B per chunk (cl, cs)",
+                     "moved_bytes_per_launch": moved,
+                     "moved_bytes_basis": "the x-window format: 10 B per slot (FP64 value + 16-bit window "
+                                          "position), x and y once, chunk metadata and window tables",
+                     "achieved_moved_bytes": round(achieved_moved, 1),
+                     "frac_moved_bytes": round(achieved_moved / PEAK_HBM_GBS, 4),
+                     "traffic_source": ("stored FETCH_SIZE + WRITE_SIZE counter measurement "
+                                        "(profiles/traffic_stencil27_160_fp64.json), copy-calibrated, taken on "
+                                        "kernel sources with hash %s" % src_hash) if traffic else
+                                       "null: no counter measurement for the current kernel sources (hash %s)"
+                                       % src_hash},
+        "model": model_report(model, probes["read_gbs"], gfs, achieved_moved, inf, A, sizes, traffic),
         "build_ms": round(build_s * 1e3, 2),
         "probes": probes,
         "kernel_source_hash": src_hash,
@@ -524,23 +588,27 @@ def main():
         h.close()
         print(json.dumps(line))
         return
-    # precision forms on the same matrix, at the headline C and at C = 64, with
-    # the normwise error against the FP64 product of the same rounded x
-    forms, errs = {}, {}
+    checks, checks_x = [], {"stencil27_160": (A, x_np)}
+    progress("headline %.2f GF/s; precision forms" % gfs)
+    # precision forms on the same matrix (values FP32 / BF16, x rounded to
+    # FP32, accumulation FP32 / FP64), at the headline C and at C = 64, with
+    # the x window (16-bit window positions) and with the int32 column
+    # indices; the results go to the oracle leg for their errors
+    forms = {"x_window_uint16_positions": {}, "int32_col_indices": {}}
     xf = x.float()
-    y64 = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
-    sellcs.sell_spmv(h, xf.double(), y64)
-    for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
-        for C in sorted({HEADLINE["C"], 64}):
-            hf = sellcs.sell_build(r, c, v, A.ncols, C, HEADLINE["sigma"], val_dtype=vd, acc_dtype=ad)
-            yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
-            t = time_calls(lambda: sellcs.sell_spmv(hf, xf, yf), max(50, args.steps // 4), 10)
-            key = "%s_val_%s_acc_C%d" % (vd, ad, C)
-            forms[key] = round(2.0 * A.nnz / t * 1e-9, 2)
-            errs[key] = float("%.3g" % normwise(yf, y64))
-            hf.close()
+    for path, xw in (("x_window_uint16_positions", 0), ("int32_col_indices", -1)):
+        for vd, ad in (("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")):
+            for C in sorted({HEADLINE["C"], 64}):
+                hf = sellcs.sell_build(r, c, v, A.ncols, C, HEADLINE["sigma"], val_dtype=vd, acc_dtype=ad, xwindow=xw)
+                if hf.info["xwindow"] != (1 if xw == 0 else 0):
+                    raise RuntimeError("%s: unexpected x path for %s/%s C=%d" % (path, vd, ad, C))
+                yf = torch.empty(A.nrows, dtype=torch.float64 if ad == "f64" else torch.float32, device="cuda")
+                t = time_calls(lambda: sellcs.sell_spmv(hf, xf, yf), max(50, args.steps // 4), 10)
+                key = "%s_val_%s_acc_C%d" % (vd, ad, C)
+                forms[path][key] = round(2.0 * A.nnz / t * 1e-9, 2)
+                checks.append(("stencil27_160", "%s.%s" % (path, key), vd, yf.double().cpu().numpy()))
+                hf.close()
     line["forms_stencil27_160_gfs"] = forms
-    line["forms_stencil27_160_normwise_err_vs_fp64"] = errs
     # the paper's comparison on one device: CRS (one lane per row, and L lanes
     # per row with a cross-lane reduction) against SELL-C-sigma
     crs = {}
@@ -565,9 +633,10 @@ def main():
     h.close()
     del r, c, v
     if not args.no_forms:
-        line["forms"] = run_forms(args, probes)
+        line["forms"] = run_forms(args, probes, checks, checks_x)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(A, x_np, C=HEADLINE["C"], sigma=HEADLINE["sigma"])
+        progress("CPU oracle leg")
+        line["cpu_baseline"], line["errors_vs_oracle"] = cpu_baseline_leg(A, x_np, y_head, checks, checks_x)
     print(json.dumps(line))
 
 

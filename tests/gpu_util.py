@@ -67,12 +67,21 @@ def spmv_gpu(h, x_np, dtype=None):
     return y.double().cpu().numpy()
 
 
-def check_fp64(A, y, x, tol=1e-13):
-    """|y - y_ref|_i <= tol * (|A||x|)_i, y_ref from the long double oracle."""
+def check_fp64(A, y, x, tol=1e-13, m=None):
+    """|y - y_ref|_i <= tol * (|A||x|)_i, y_ref from the long double oracle.
+    With m (per-row bound on the roundings a term goes through on the GPU,
+    see chain_per_row) the bound is the smaller of tol and the one the
+    summation chain guarantees: gamma_{m_i+1} (the +1 covers the rounding of
+    y_ref to double) plus the oracle's own long double chain."""
     yh = oracle.crs_spmv_hi(A, x)
     ax = oracle.crs_absmv(A, x)
     err = np.abs(y - yh)
-    ok = err <= tol * ax
+    bound = tol * ax
+    if m is not None:
+        lens = A.row_lengths()
+        g = gamma(np.asarray(m) + 1, U["f64"]) * 1.0001 + gamma(lens, 2.0 ** -64)
+        bound = np.minimum(tol, g) * ax
+    ok = err <= bound
     assert np.all(np.isfinite(y))
     assert np.all(ok), "max rel err %g at %d" % (np.max(err / np.where(ax > 0, ax, 1)), int(np.argmax(~ok)))
     return float(np.max(err / np.where(ax > 0, ax, 1)))
@@ -85,6 +94,38 @@ def chunk_width_per_row(A, lay, C):
     return lay["cl"][inv // C].astype(np.int64)
 
 
+def chain_per_row(A, h, C, block=False):
+    """Per-row bound m_i on the roundings one product term goes through in
+    the GPU product of handle h (FMA: one rounding per term added):
+      * the terms one lane adds in turn: its share ceil(w / T) of the row's
+        chunk width w, T the lanes per row (the block-form kernels keep a
+        whole row in one lane, T = 1); of the segment width S instead where
+        the chunk is split into segments on different waves;
+      * log2(T) cross-lane additions;
+      * the additions of a split row's segment sums, in segment order."""
+    from paper_1307_6209_amd import sellcs
+    inf = h.info
+    w = chunk_width_per_row(A, sellcs.sell_export(h, parts=("perm", "cl")), C)
+    T = 1 if block else int(inf["lanes_per_row"])
+    S = int(inf["seg_cols"])
+    split = (inf["nsplit"] > 0) & (w > S)
+    nseg = np.where(split, -(-w // S), 0)
+    width = np.where(split, S, w)
+    return -(-width // T) + (T.bit_length() - 1) + nseg
+
+
+def batch_chain_per_row(A, h, C):
+    """chain_per_row for the batched launch, which loads one slot per lane
+    (T = 64 / min(C, 64)) and cuts chunks at a segment width S of its own (a
+    multiple of 64, so of T). For a split row S/T + ceil(w/S) <= w/T + 2
+    whatever S is (the left side is convex in S and equals w/T + 1 at S = T
+    and S = w), so the bound holds without knowing S."""
+    from paper_1307_6209_amd import sellcs
+    w = chunk_width_per_row(A, sellcs.sell_export(h, parts=("perm", "cl")), C)
+    T = 64 // min(C, 64)
+    return -(-w // T) + (T.bit_length() - 1) + 2
+
+
 def rounded_values(A, val_dtype):
     if val_dtype == "f32":
         return oracle.round_f32(A.val).astype(np.float64)
@@ -93,30 +134,30 @@ def rounded_values(A, val_dtype):
     return A.val
 
 
-def check_reduced(A, h, x, val_dtype, acc, C, nseg_max=1):
-    """Reduced-precision forms. Kernel check against y_q (the exact product of
-    the rounded values and rounded x, in long double):
-        |y - y_q|_i <= gamma_acc(m_i) (|A^||x^|)_i,
-    m_i = chunk width + log2(64) + nseg + 1 (a bound on the summation chain).
+def check_reduced(A, h, x, val_dtype, acc, C):
+    """Reduced-precision forms, with m_i the per-row chain of chain_per_row
+    and u_acc the unit roundoff of the accumulation type. Kernel check
+    against y_q (the exact product of the rounded values and rounded x, in
+    long double, rounded once to double):
+        |y - y_q|_i <= gamma_acc(m_i + 1) (|A^||x^|)_i.
     Against the double product of A and x^:
-        |y - A x^|_i <= [u_v + (1 + u_v) gamma_acc(m_i)] (|A||x^|)_i.
+        |y - A x^|_i <= [u_v + (1 + u_v) gamma_acc(m_i + 1)] (|A||x^|)_i.
     Returns (max componentwise, normwise) error against A x^."""
     xr = oracle.round_f32(x).astype(np.float64)
-    return check_reduced_y(A, spmv_gpu(h, xr), h, x, val_dtype, acc, C, nseg_max)
+    return check_reduced_y(A, spmv_gpu(h, xr), h, x, val_dtype, acc, C)
 
 
-def check_reduced_y(A, y, h, x, val_dtype, acc, C, nseg_max=1):
+def check_reduced_y(A, y, h, x, val_dtype, acc, C, m=None):
     """The bounds of check_reduced for a result y computed elsewhere (the
-    batched launch) from the layout of handle h."""
-    from paper_1307_6209_amd import sellcs
+    batched launch passes its own chain m) from the layout of handle h."""
     xr = oracle.round_f32(x).astype(np.float64)
     vr = rounded_values(A, val_dtype)
     yq = oracle.crs_spmv_hi(A, xr, val=vr)
     aq = oracle.crs_absmv(A, xr, val=vr)
-    lay = sellcs.sell_export(h)
-    m = chunk_width_per_row(A, lay, C) + 8 + nseg_max
-    ua = 2.0 ** -53 if acc == "f64" else 2.0 ** -24
-    g = gamma(m, ua)
+    if m is None:
+        m = chain_per_row(A, h, C)
+    ua = U[acc]
+    g = gamma(np.asarray(m) + 1, ua) + gamma(A.row_lengths(), 2.0 ** -64)
     assert np.all(np.isfinite(y))
     assert np.all(np.abs(y - yq) <= g * aq * 1.0001 + 1e-300)
     yref = oracle.crs_spmv_hi(A, xr)

@@ -29,3 +29,27 @@ def test_paper_context_is_context_only():
     ctx = bench.PAPER_CONTEXT
     assert set(ctx["model_ceiling_gfs"]) == {"snb", "xeon_phi", "k20"}
     assert "context" in ctx["note"]
+
+
+def test_errors_against_the_oracle_on_host():
+    """The benchmark's error report: zero for the oracle's own products, and
+    the normwise / componentwise errors of a known perturbation."""
+    import numpy as np
+    import bench
+    import oracle
+    import synth
+    A = synth.lap5(12)
+    x = synth.uniform(A.ncols, 7)
+    xr = oracle.round_f32(x).astype(np.float64)
+    y = oracle.crs_spmv_hi(A, x)
+    yq = oracle.crs_spmv_hi(A, xr)
+    bad = yq.copy()
+    bad[5] += 1e-3
+    out = bench.errors_vs_oracle(y, [("stencil27_160", "exact", "f32", yq), ("stencil27_160", "bad", "f32", bad)],
+                                 {"stencil27_160": (A, x)})
+    assert out["headline_fp64"]["normwise"] == 0 and out["headline_fp64"]["componentwise"] == 0
+    assert out["stencil27_160"]["exact"] == {"normwise": 0.0, "componentwise": 0.0}
+    scale = oracle.crs_absmv(A, xr)
+    want_c = float("%.3g" % (1e-3 / scale[5]))
+    want_n = float("%.3g" % (1e-3 / np.linalg.norm(yq)))
+    assert out["stencil27_160"]["bad"] == {"normwise": want_n, "componentwise": want_c}

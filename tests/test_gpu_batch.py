@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import build, check_fp64, check_reduced_y, say
+from gpu_util import batch_chain_per_row, build, check_fp64, check_reduced_y, say
 
 pytestmark = pytest.mark.gpu
 
@@ -45,13 +45,13 @@ def test_batch_fp64(C, form):
     xs = [synth.uniform(A.ncols, 50 + i, 1) for i, A in enumerate(mats)]
     say("batch C", C, "rows", sum(A.nrows for A in mats))
     ys = run(b, mats, xs, (torch.float64, torch.float64))
-    for A, x, y in zip(mats, xs, ys):
-        check_fp64(A, y, x)
+    for A, h, x, y in zip(mats, hs, xs, ys):
+        check_fp64(A, y, x, m=batch_chain_per_row(A, h, C))
     # a second call with new vectors (the pointer table is rewritten)
     xs2 = [synth.uniform(A.ncols, 80 + i, 1) for i, A in enumerate(mats)]
     ys2 = run(b, mats, xs2, (torch.float64, torch.float64))
-    for A, x, y in zip(mats, xs2, ys2):
-        check_fp64(A, y, x)
+    for A, h, x, y in zip(mats, hs, xs2, ys2):
+        check_fp64(A, y, x, m=batch_chain_per_row(A, h, C))
     b.close()
 
 
@@ -87,7 +87,7 @@ def test_batch_reduced(val_dtype, acc, form):
     xs = [oracle.round_f32(synth.uniform(A.ncols, 60 + i, 1)).astype(np.float64) for i, A in enumerate(mats)]
     ys = run(b, mats, xs, (torch.float32, torch.float64 if acc == "f64" else torch.float32))
     for A, h, x, y in zip(mats, hs, xs, ys):
-        comp, norm = check_reduced_y(A, y, h, x, val_dtype, acc, 32, nseg_max=64)
+        comp, norm = check_reduced_y(A, y, h, x, val_dtype, acc, 32, m=batch_chain_per_row(A, h, 32))
         say("batch", form, val_dtype, acc, "componentwise %.3g normwise %.3g" % (comp, norm))
 
 

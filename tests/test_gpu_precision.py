@@ -26,7 +26,7 @@ def test_reduced_precision_bounds(val_dtype, acc, vec, name, make, C, sigma):
     A = make()
     x = synth.uniform(A.ncols, 31, 1)
     h = build(A, C, sigma, val_dtype=val_dtype, acc_dtype=acc, vec=vec)
-    comp, norm = check_reduced(A, h, x, val_dtype, acc, C, nseg_max=h.info["nsplit"] and 64)
+    comp, norm = check_reduced(A, h, x, val_dtype, acc, C)
     say("precision", name, val_dtype, acc, "componentwise %.3g normwise %.3g" % (comp, norm))
 
 
@@ -36,4 +36,4 @@ def test_reduced_precision_split(val_dtype, acc):
     x = synth.uniform(A.ncols, 32, 1)
     h = build(A, 16, 1, val_dtype=val_dtype, acc_dtype=acc, seg_cols=64)
     assert h.info["nsplit"] > 0
-    check_reduced(A, h, x, val_dtype, acc, 16, nseg_max=int(A.row_lengths().max()) // 20 + 2)
+    check_reduced(A, h, x, val_dtype, acc, 16)

@@ -2,15 +2,15 @@
 (random, banded, power-law, stencil, Laplacian), C, sigma, value and
 accumulation types, slots per lane, unroll, split width, x path and, for
 FP64 handles, the block form. Every result is checked against the oracle
-with a bound built from the summation chain of each row (its chunk width,
-the cross-lane sum and the segments of a split row), so the sweep holds for
-any combination the options allow."""
+with the bound of the summation chain of each row (the terms one lane adds,
+the cross-lane sum and the segments of a split row), capped at
+1e-13 (|A||x|)_i for FP64."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_util import build, chunk_width_per_row, check_reduced, dev_crs, gamma, say, spmv_gpu
+from gpu_util import build, chain_per_row, check_fp64, check_reduced, say, spmv_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -46,20 +46,6 @@ def matrix(rng, case):
     return "lap5", synth.lap5(int(rng.integers(4, 70)))
 
 
-def check_fp64_chain(A, h, C, y, x):
-    """|y - y_hi|_i <= gamma_m (|A||x|)_i, m = chunk width of row i + 8 +
-    segments: every product is one rounding into the lane's sum, then at most
-    log2(64) cross-lane additions and the additions of the segments."""
-    inf = h.info
-    nseg = 1 + (-(-inf["max_row_len"] // inf["seg_cols"]) if inf["nsplit"] > 0 else 0)
-    from paper_1307_6209_amd import sellcs
-    m = chunk_width_per_row(A, sellcs.sell_export(h, parts=("perm", "cl")), C) + 8 + nseg
-    yh = oracle.crs_spmv_hi(A, x)
-    ay = oracle.crs_absmv(A, x)
-    assert np.all(np.isfinite(y))
-    assert np.all(np.abs(y - yh) <= gamma(m, 2.0 ** -53) * ay * 1.0001 + 1e-300)
-
-
 @pytest.mark.parametrize("case", range(160))
 def test_random_configuration(case):
     from paper_1307_6209_amd import sellcs
@@ -91,7 +77,7 @@ def test_random_configuration(case):
     x = synth.uniform(A.ncols, 500 + case, 1)
     if val_dtype == "f64":
         y = spmv_gpu(h, x)
-        check_fp64_chain(A, h, C, y, x)
+        check_fp64(A, y, x, m=chain_per_row(A, h, C))
         assert np.array_equal(spmv_gpu(h, x).view(np.uint64), y.view(np.uint64))
         if C >= 8 and A.nrows > 0:
             k = int(rng.choice([2, 3, 8, 16, 32, 40, 64, 100]))
@@ -106,8 +92,8 @@ def test_random_configuration(case):
             sellcs.sell_spmmv(h, Xd, Y)
             torch.cuda.synchronize()
             Yc = Y.cpu().numpy()
+            m = chain_per_row(A, h, C, block=True)
             for v in range(k):
-                check_fp64_chain(A, h, C, Yc[:, v].copy(), X[:, v].copy())
+                check_fp64(A, Yc[:, v].copy(), X[:, v].copy(), m=m)
     else:
-        nseg = 1 + (-(-inf["max_row_len"] // inf["seg_cols"]) if inf["nsplit"] > 0 else 0)
-        check_reduced(A, h, x, val_dtype, acc, C, nseg_max=nseg)
+        check_reduced(A, h, x, val_dtype, acc, C)
