@@ -203,6 +203,31 @@ sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream);
 sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t k,
                        void *stream);
 
+/*
+ * sell_spmmv_noalloc -- sell_spmmv for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same result bit for bit, but
+ * the segment sums of split chunks go to a statically allocated scratch
+ * array of 64 MiB per device (held until the process ends) instead of the
+ * handle's buffer, so k is not limited by the kmax given at build. The call
+ * allocates nothing and calls no allocating routine; the first call on a
+ * device looks up that device's address of the array.
+ *
+ * Arguments, layouts, ownership and the finite-X precondition as in
+ * sell_spmmv (k = 1 runs the sell_spmv kernels). The handle's device must be
+ * the current device (else SELL_ERR_INVALID_ARG). SELL_ERR_UNSUPPORTED,
+ * naming the bytes needed, when the segment sums exceed the 64 MiB: for a
+ * handle with split chunks they take (rows of split slices) x k doubles
+ * (pass kernel: k rounded up to its pass width); handles without split
+ * chunks use no scratch. Every call on one device shares that device's
+ * array and leaves its contents there (nothing in it needs clearing: each
+ * call writes every sum before reading it), so calls that overlap in time
+ * on one device -- on different streams, or from different threads -- race
+ * and must be serialised by the caller.
+ */
+sell_status sell_spmmv_noalloc(sell_handle h, const void *X, void *Y, int32_t k,
+                               void *stream);
+
 /* sell_info -- host copy of the handle's sizes and parameters. */
 sell_status sell_info(sell_handle h, sell_info_t *info);
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -490,11 +491,17 @@ sell::SpmvArgs args_of(const sell_matrix *h, const void *x, void *y) {
 
 }  // namespace
 
-extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream) {
-  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_spmv: null handle");
-  if ((h->nrows > 0 && !y) || (h->ncols > 0 && !x)) return fail(SELL_ERR_INVALID_ARG, "sell_spmv: null vector");
+namespace {
+
+// The product on handle h; `partial` (non-null) replaces the handle's
+// partial-sum buffer for the segment sums of split chunks.
+sell_status spmv_run(sell_handle h, const void *x, void *y, void *stream, void *partial, const char *who) {
+  if (!h) return fail(SELL_ERR_INVALID_ARG, std::string(who) + ": null handle");
+  if ((h->nrows > 0 && !y) || (h->ncols > 0 && !x))
+    return fail(SELL_ERR_INVALID_ARG, std::string(who) + ": null vector");
   if (h->nrows == 0) return SELL_OK;
   sell::SpmvArgs a = args_of(h, x, y);
+  if (partial) a.partial = partial;
   // padding-heavy layouts skip the gathers of their zero slots; near-dense
   // chunks skip the per-slot test
   const bool skip_zero = h->beta < 0.9;
@@ -506,8 +513,14 @@ extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *st
   } else {
     e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a, static_cast<hipStream_t>(stream));
   }
-  if (e != hipSuccess) return hip_fail("sell_spmv launch", e);
+  if (e != hipSuccess) return hip_fail((std::string(who) + " launch").c_str(), e);
   return SELL_OK;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_spmv(sell_handle h, const void *x, void *y, void *stream) {
+  return spmv_run(h, x, y, stream, nullptr, "sell_spmv");
 }
 
 
@@ -528,15 +541,39 @@ int choose_kv(const sell_matrix *h, int k, int ktile) {
 
 }  // namespace
 
-extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t k, void *stream) {
-  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: null handle");
-  if (k < 1) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k must be >= 1");
-  if ((h->nrows > 0 && !Y) || (h->ncols > 0 && !X)) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: null block");
-  if (h->combo != sell::COMBO_F64_F64) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: FP64 handles only");
+namespace {
+
+// Doubles of partial sums a block product of width k needs on handle h with
+// passes of width kt (the one-pass row kernels: kt = k).
+int64_t partial_doubles(const sell_matrix *h, int64_t k, int64_t kt) {
+  if (!h->units || h->nsplit == 0) return 0;
+  const int64_t ntiles = (k + kt - 1) / kt;
+  return h->nsegs * (int64_t)h->g.rpw * ntiles * kt;
+}
+
+// The block product on handle h. scratch == nullptr: the handle's
+// partial-sum buffer (sized at build for kmax); else a buffer of
+// scratch_bytes bytes for the segment sums of split chunks.
+sell_status spmmv_run(sell_handle h, const void *X, void *Y, int32_t k, void *stream, void *scratch,
+                      size_t scratch_bytes, const char *who) {
+  const std::string w = who;
+  if (!h) return fail(SELL_ERR_INVALID_ARG, w + ": null handle");
+  if (k < 1) return fail(SELL_ERR_INVALID_ARG, w + ": k must be >= 1");
+  if ((h->nrows > 0 && !Y) || (h->ncols > 0 && !X)) return fail(SELL_ERR_INVALID_ARG, w + ": null block");
+  if (h->combo != sell::COMBO_F64_F64) return fail(SELL_ERR_UNSUPPORTED, w + ": FP64 handles only");
   if (h->nrows == 0) return SELL_OK;
-  if (k == 1) return sell_spmv(h, X, Y, stream);
-  if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: C must be >= 8 for k > 1");
-  if (h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv: k exceeds the kmax given at build");
+  auto too_big = [&](int64_t doubles) {
+    return fail(SELL_ERR_UNSUPPORTED, w + ": the segment sums of split chunks need " +
+                                          std::to_string(doubles * (int64_t)sizeof(double)) +
+                                          " bytes of scratch, more than its " + std::to_string(scratch_bytes));
+  };
+  if (k == 1) {
+    if (scratch && partial_doubles(h, 1, 1) * (int64_t)sizeof(double) > (int64_t)scratch_bytes)
+      return too_big(partial_doubles(h, 1, 1));
+    return spmv_run(h, X, Y, stream, scratch, who);
+  }
+  if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, w + ": C must be >= 8 for k > 1");
+  if (!scratch && h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, w + ": k exceeds the kmax given at build");
   // With the automatic pass width, k = 16, 32 and 64 run in one pass with
   // LPR lanes per row: each row of X is read whole by one access (X and Y
   // aligned to the k/LPR doubles of a lane). More lanes per row suit dense
@@ -551,11 +588,14 @@ extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t
     const int lpr = k == 64 ? 16 : k == 32 ? (dense ? 16 : 8) : (k == 16 && dense) ? 8 : 0;
     if (h->ktile == 0 && lpr > 0 && h->C >= 16 &&
         ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % (sizeof(double) * (k / lpr))) == 0) {
+      if (scratch && partial_doubles(h, k, k) * (int64_t)sizeof(double) > (int64_t)scratch_bytes)
+        return too_big(partial_doubles(h, k, k));
       sell::SpmvArgs a = args_of(h, X, Y);
+      if (scratch) a.partial = scratch;
       a.k = k;
       a.kt = k;
       hipError_t e = sell::launch_spmmv_rows(h->C, lpr, a, static_cast<hipStream_t>(stream));
-      if (e != hipSuccess) return hip_fail("sell_spmmv launch", e);
+      if (e != hipSuccess) return hip_fail((w + " launch").c_str(), e);
       return SELL_OK;
     }
   }
@@ -567,14 +607,66 @@ extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t
     kv >>= 1;
   const int KT = (64 / h->g.rpw) * kv;
   const int64_t ntiles = (k + KT - 1) / KT;
-  if (h->units && ntiles * KT > next_pow2(h->kmax))
-    return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv: pass width exceeds the partial-sum buffer");
+  if (!scratch && h->units && ntiles * KT > next_pow2(h->kmax))
+    return fail(SELL_ERR_UNSUPPORTED, w + ": pass width exceeds the partial-sum buffer");
+  if (scratch && partial_doubles(h, k, KT) * (int64_t)sizeof(double) > (int64_t)scratch_bytes)
+    return too_big(partial_doubles(h, k, KT));
   sell::SpmvArgs a = args_of(h, X, Y);
+  if (scratch) a.partial = scratch;
   a.k = k;
   a.kt = KT;
   hipError_t e = sell::launch_spmmv(h->C, kv, a, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail("sell_spmmv launch", e);
+  if (e != hipSuccess) return hip_fail((w + " launch").c_str(), e);
   return SELL_OK;
+}
+
+// Scratch of sell_spmmv_noalloc: the segment sums of split chunks, in a
+// statically allocated device array (every GPU the library runs on holds its
+// own copy until the process ends). Host code reaches it only through the
+// device address hipGetSymbolAddress returns for the current device; the
+// array's name in host code is a host-side stand-in, not that address.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of the scratch array, looked up once per
+// device (with that device current) and kept.
+sell_status scratch_for_current_device(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail("sell_spmmv_noalloc: hipGetDevice", e);
+  if (dev < 0 || dev >= kMaxDevices) return fail(SELL_ERR_UNSUPPORTED, "sell_spmmv_noalloc: device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail("sell_spmmv_noalloc: hipGetSymbolAddress(scratch)", e);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SELL_OK;
+}
+
+}  // namespace
+
+extern "C" sell_status sell_spmmv(sell_handle h, const void *X, void *Y, int32_t k, void *stream) {
+  return spmmv_run(h, X, Y, k, stream, nullptr, 0, "sell_spmmv");
+}
+
+extern "C" sell_status sell_spmmv_noalloc(sell_handle h, const void *X, void *Y, int32_t k, void *stream) {
+  if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_spmmv_noalloc: null handle");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail("sell_spmmv_noalloc: hipGetDevice", e);
+  if (dev != h->device)
+    return fail(SELL_ERR_INVALID_ARG, "sell_spmmv_noalloc: the handle's device must be the current device");
+  void *p = nullptr;
+  sell_status st = scratch_for_current_device(&p);
+  if (st != SELL_OK) return st;
+  return spmmv_run(h, X, Y, k, stream, p, kScratchBytes, "sell_spmmv_noalloc");
 }
 
 // ===========================================================================

@@ -80,6 +80,7 @@ SIGNATURES = {
                                   ctypes.POINTER(c_p)]),
     "sell_spmv": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
     "sell_spmmv": (ctypes.c_int, [c_p, c_p, c_p, c_i32, c_p]),
+    "sell_spmmv_noalloc": (ctypes.c_int, [c_p, c_p, c_p, c_i32, c_p]),
     "sell_info": (ctypes.c_int, [c_p, ctypes.POINTER(SellInfo)]),
     "sell_export": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_p, c_p]),
     "sell_export_xwindow": (ctypes.c_int, [c_p, c_p, c_p, c_p]),
@@ -279,16 +280,27 @@ def sell_spmv(h: SellMatrix, x, y, stream=None):
     return y
 
 
-def sell_spmmv(h: SellMatrix, X, Y, stream=None):
-    """Y = A X for row-major X (ncols x k) and Y (nrows x k)."""
+def _block_args(h: SellMatrix, X, Y):
     if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
         raise ValueError("X and Y must be 2-D with the same number of columns")
-    k = X.shape[1]
     if X.shape[0] != h.info["ncols"] or Y.shape[0] != h.info["nrows"]:
         raise ValueError("X must be ncols x k and Y nrows x k")
-    xp = _dptr(X, h.x_dtype, "X")
-    yp = _dptr(Y, h.y_dtype, "Y")
+    return _dptr(X, h.x_dtype, "X"), _dptr(Y, h.y_dtype, "Y"), X.shape[1]
+
+
+def sell_spmmv(h: SellMatrix, X, Y, stream=None):
+    """Y = A X for row-major X (ncols x k) and Y (nrows x k)."""
+    xp, yp, k = _block_args(h, X, Y)
     _check(lib().sell_spmmv(h.handle, xp, yp, k, _stream(stream)), "sell_spmmv")
+    return Y
+
+
+def sell_spmmv_noalloc(h: SellMatrix, X, Y, stream=None):
+    """sell_spmmv with the segment sums of split chunks in the library's
+    static per-device scratch (no device allocation; k not bounded by the
+    kmax given at build; overlapping calls on one device race)."""
+    xp, yp, k = _block_args(h, X, Y)
+    _check(lib().sell_spmmv_noalloc(h.handle, xp, yp, k, _stream(stream)), "sell_spmmv_noalloc")
     return Y
 
 
