@@ -459,6 +459,40 @@ def block_pass(args):
                       "padded": inf["padded"], "beta": inf["beta"], "nsplit": inf["nsplit"], "rows": rows}))
 
 
+def batch_pass(args):
+    """The batched launch over the 64 power-law matrices (n log-uniform in
+    [10^3, 2*10^5]), SELL-32-n_b: time per launch of both forms, or under a
+    counter run (--pmc-pass) exactly 3 launches of each form and one copy
+    probe for the counter calibration."""
+    import torch
+    import synth
+    from paper_1307_6209_amd import sellcs
+    mats = synth.batch_workload(64)
+    devs = [to_dev(B) for B in mats]
+    xs = [torch.from_numpy(synth.uniform(B.ncols, 5 + i)).cuda() for i, B in enumerate(mats)]
+    ys = [torch.empty(B.nrows, dtype=torch.float64, device="cuda") for B in mats]
+    hs = [sellcs.sell_build(rr, cc, vv, B.ncols, 32, B.nrows) for (rr, cc, vv), B in zip(devs, mats)]
+    nnz = sum(B.nnz for B in mats)
+    rows = []
+    for form in ("sell_batch_create", "sell_batch_create_persistent"):
+        b = getattr(sellcs, form)(hs)
+        if args.pmc_pass:
+            for _ in range(3):
+                sellcs.sell_batch_spmv(b, xs, ys)
+            torch.cuda.synchronize()
+            t = float("nan")
+        else:
+            t = time_calls(lambda: sellcs.sell_batch_spmv(b, xs, ys), 200, 20)
+        rows.append({"form": form, "us": round(t * 1e6, 2), "gfs": round(2.0 * nnz / t * 1e-9, 2)})
+        b.close()
+    if args.pmc_pass:
+        sellcs.sell_probe_bandwidth(1, 1 << 30, 1)
+        torch.cuda.synchronize()
+    print(json.dumps({"batch_pass": "powerlaw x 64", "C": 32, "sigma": "n_b", "rows_total": sum(B.nrows for B in mats),
+                      "nnz": nnz, "padded": sum(h.info["padded"] for h in hs),
+                      "x_bytes": 8 * sum(B.ncols for B in mats), "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,8 +507,10 @@ def main():
     ap.add_argument("--sigma-sweep", action="store_true", help="SELL-32-sigma sweep on the power-law matrix")
     ap.add_argument("--block-pass", action="store_true",
                     help="block form k = 16, 32, 64 on the power-law 1M matrix (with --pmc-pass: for counters)")
+    ap.add_argument("--batch-pass", action="store_true",
+                    help="batched launch over 64 power-law matrices (with --pmc-pass: for counters)")
     ap.add_argument("--probe-sweep", action="store_true",
-                    help="random-gather probe over array sizes 1 MiB .. 4 GiB, and the read probe")
+                    help="random-gather and random-row probes over array sizes 1 MiB .. 4 GiB, and the read probe")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the SELL-C-sigma product here is a single-device kernel "
@@ -492,11 +528,20 @@ def main():
     if args.block_pass:
         block_pass(args)
         return
+    if args.batch_pass:
+        batch_pass(args)
+        return
     if args.probe_sweep:
         res = {"read_4gib_gbs": round(sellcs.sell_probe_bandwidth(0, 4 << 30, 10), 1)}
         for mib in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 4096):
             g = sellcs.sell_probe_bandwidth(2, mib << 20, 5)
             res["gather_%dmib_ggather_per_s" % mib] = round(g / 8.0, 1)
+        # random whole rows of 128 / 256 / 512 bytes (the block form's X rows
+        # at k = 16 / 32 / 64), in G rows/s
+        for kind, rb in ((3, 128), (4, 256), (5, 512)):
+            for mib in (4, 16, 64, 128, 256, 512, 1024, 4096):
+                g = sellcs.sell_probe_bandwidth(kind, mib << 20, 5)
+                res["rows%d_%dmib_grows_per_s" % (rb, mib)] = round(g / rb, 2)
         print(json.dumps({"probe_sweep": res}))
         return
     A = synth.workload(HEADLINE["workload"])

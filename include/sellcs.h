@@ -411,9 +411,15 @@ sell_status sell_batch_autotune(const sell_crs *As, int32_t count,
  * positions of an array of the largest power-of-two size <= bytes (the
  * x-vector accesses of a matrix without column locality); *gbs is then
  * 8 bytes x gathers / time, so gathers per second = *gbs / 8 x 1e9.
+ * kinds 3, 4, 5 are the random-row rate of the block form (sell_spmmv reads
+ * the k right-hand sides of a column as one row of 8k bytes): rows of 128,
+ * 256 or 512 bytes (k = 16, 32, 64) at hashed row positions of an array of
+ * the largest power-of-two row count that fits in bytes, 16 bytes per lane;
+ * *gbs is then row bytes x rows / time (rows per second = *gbs / row bytes
+ * x 1e9).
  * Runs reps timed passes after one warm-up on stream; *gbs receives the mean
  * bandwidth in GB/s (1e9 bytes). Allocates and frees its own buffers.
- * Errors: SELL_ERR_INVALID_ARG for kind outside 0..2, reps < 1 or bytes
+ * Errors: SELL_ERR_INVALID_ARG for kind outside 0..5, reps < 1 or bytes
  * below 1 MiB; SELL_ERR_OOM when the buffers cannot be allocated.
  */
 sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps,

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_plan.h"
 #include "sell_internal.h"
 
 using sell::Geom;
@@ -823,10 +824,14 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
   DeviceInfo di = device_info();
   const int32_t S = auto_seg_cols(total, g.T, di.cus);
   B->seg_cols = S;
-  // split units of every matrix first (the longest work starts earliest),
-  // then the whole items; one wave per unit
-  std::vector<sell::BUnit> units;
+  // work units of every matrix: the segments of its split chunks, then its
+  // whole chunks; cost estimate of a unit: its wave steps plus a fixed charge
+  std::vector<sell::BUnit> all;
   std::vector<sell::BSplitDesc> splits;
+  std::vector<int32_t> umat;
+  std::vector<int64_t> ucost;
+  std::vector<uint8_t> usplit;
+  const int64_t kFixed = 4;
   int64_t off = 0;
   for (int32_t b = 0; b < count; ++b) {
     const ItemCols &s = st[b];
@@ -837,42 +842,45 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
       const int32_t sid = (int32_t)splits.size();
       splits.push_back({b, (int32_t)it, nseg, 0, off});
       off += (int64_t)nseg * g.rpw;
-      for (int32_t q = 0; q < nseg; ++q) units.push_back({b, (int32_t)it, q, nseg, sid, {0, 0, 0}});
+      for (int32_t q = 0; q < nseg; ++q) {
+        all.push_back({b, (int32_t)it, q, nseg, sid, {0, 0, 0}});
+        const int64_t cols = std::min<int64_t>(S, (int64_t)w - (int64_t)q * S);
+        umat.push_back(b);
+        ucost.push_back((cols + g.T - 1) / g.T + kFixed);
+        usplit.push_back(1);
+      }
+    }
+    for (size_t it = 0; it < s.cols.size(); ++it) {
+      const int32_t w = s.cols[it];
+      if (w > S) continue;
+      all.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
+      umat.push_back(b);
+      ucost.push_back((w + g.T - 1) / g.T + kFixed);
+      usplit.push_back(0);
     }
   }
-  for (int32_t b = 0; b < count; ++b) {
-    const ItemCols &s = st[b];
-    for (size_t it = 0; it < s.cols.size(); ++it)
-      if (s.cols[it] <= S) units.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
-  }
-  B->nunits = (int64_t)units.size();
   B->nsplit = (int64_t)splits.size();
-  if (B->nunits >= ((int64_t)1 << 31)) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_create: too many work units");
 
-  // persistent form: one slice of equal estimated cost (wave steps plus a
-  // fixed charge per unit) for each resident wave
-  std::vector<int32_t> slice;
+  // placement on the XCDs: each matrix (or piece of a large one) on one XCD,
+  // so that its x stays in that XCD's L2 (batch_plan.h). One unit per wave
+  // (filler slots where an XCD's queue is shorter), or the persistent form's
+  // equal-cost slices per resident wave.
+  int64_t nwaves = 0;
   if (persistent) {
     const int wpcu = std::max(1, sell::batch_waves_per_cu(B->combo, B->C, B->U));
-    int64_t nwaves = std::max<int64_t>(4, std::min<int64_t>((int64_t)di.cus * wpcu, B->nunits));
-    nwaves = (nwaves + 3) / 4 * 4;
-    const int64_t kFixed = 4;
-    std::vector<int64_t> cost(units.size());
-    int64_t tot_cost = 0;
-    for (size_t q = 0; q < units.size(); ++q) {
-      const sell::BUnit &u = units[q];
-      const int64_t w = st[u.mat].cols[(size_t)u.item];
-      const int64_t cols = u.nseg > 1 ? std::min<int64_t>(S, w - (int64_t)u.seg * S) : w;
-      cost[q] = (cols + g.T - 1) / g.T + kFixed;
-      tot_cost += cost[q];
-    }
-    slice.assign((size_t)nwaves + 1, (int32_t)B->nunits);
-    slice[0] = 0;
-    int64_t acc = 0, w = 1;
-    for (size_t q = 0; q < units.size() && w < nwaves; ++q) {
-      acc += cost[q];
-      while (w < nwaves && acc * nwaves >= w * tot_cost) slice[(size_t)w++] = (int32_t)(q + 1);
-    }
+    const int64_t per_round = (int64_t)sell::kWavesPerBlock * sell::kXcds;
+    nwaves = std::min<int64_t>((int64_t)di.cus * wpcu, (int64_t)all.size());
+    nwaves = std::max<int64_t>(per_round, (nwaves + per_round - 1) / per_round * per_round);
+  }
+  const sell::XcdPlan plan =
+      sell::plan_xcd(umat, ucost, usplit, count, sell::kWavesPerBlock, sell::kXcds, nwaves);
+  std::vector<sell::BUnit> units(plan.order.size());
+  for (size_t i = 0; i < plan.order.size(); ++i)
+    units[i] = plan.order[i] < 0 ? sell::BUnit{-1, 0, 0, 1, 0, {0, 0, 0}} : all[(size_t)plan.order[i]];
+  B->nunits = (int64_t)units.size();
+  if (B->nunits >= ((int64_t)1 << 31)) return fail(SELL_ERR_UNSUPPORTED, "sell_batch_create: too many work units");
+  std::vector<int32_t> slice = plan.slice;
+  if (persistent) {
     B->persistent = true;
     B->nwaves = (int32_t)nwaves;
   }
@@ -1283,7 +1291,7 @@ extern "C" sell_status sell_batch_autotune(const sell_crs *As, int32_t count, co
 }
 
 extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps, void *stream, double *gbs) {
-  if (!gbs || reps < 1 || kind < 0 || kind > 2 || bytes < (1u << 20))
+  if (!gbs || reps < 1 || kind < 0 || kind > 5 || bytes < (1u << 20))
     return fail(SELL_ERR_INVALID_ARG, "sell_probe_bandwidth: bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   bytes = bytes / 64 * 64;
@@ -1299,7 +1307,12 @@ extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t 
     if (kind == 0) return sell::probe_read(a, bytes, sink, s);
     if (kind == 1) return sell::probe_copy(a, b, bytes / 2, s);
     hipError_t e = hipSuccess;
-    moved = sell::probe_gather(a, bytes, sink, s, &e) * (int64_t)sizeof(double);
+    if (kind == 2) {
+      moved = sell::probe_gather(a, bytes, sink, s, &e) * (int64_t)sizeof(double);
+    } else {
+      const int row_bytes = 128 << (kind - 3);  // kinds 3, 4, 5: rows of 128, 256, 512 bytes
+      moved = sell::probe_rows(a, bytes, row_bytes, sink, s, &e) * (int64_t)row_bytes;
+    }
     return e;
   };
   SELL_HIP(run());

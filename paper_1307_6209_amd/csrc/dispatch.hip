@@ -65,11 +65,11 @@ hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s) {
   if (a.nwork <= 0 || a.k <= 0) return hipSuccess;
   const int G = 64 / (C < 64 ? C : 64);
   const int KT = G * KV;
-  const unsigned nb = (unsigned)((a.nwork + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+  const unsigned nb = (unsigned)((a.nwork + kWavesPerBlock - 1) / kWavesPerBlock);
   const unsigned nt = (unsigned)((a.k + KT - 1) / KT);
 #define SELL_L(CC, KK)                                                                                       \
   if (C == CC && KV == KK) {                                                                                \
-    hipLaunchKernelGGL((dev::k_spmmv<CC, KK>), dim3(nb, nt), dim3(64 * dev::kWavesPerBlock), 0, s, a);     \
+    hipLaunchKernelGGL((dev::k_spmmv<CC, KK>), dim3(nb, nt), dim3(64 * kWavesPerBlock), 0, s, a);     \
     hipError_t e_ = hipGetLastError();                                                                      \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                       \
     hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, nt), dim3(64 * KK), 0, s, a);     \
@@ -88,12 +88,12 @@ hipError_t launch_spmmv_rows(int C, int LPR, const SpmvArgs &a, hipStream_t s) {
   if (a.nwork <= 0 || a.k <= 0) return hipSuccess;
   const int rpw = C < 64 ? C : 64;
   const int64_t waves = a.nwork * (rpw / 16);  // 16 rows per wave
-  const unsigned nb = (unsigned)((waves + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+  const unsigned nb = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   const unsigned ncomb = (unsigned)std::min(512, rpw * a.k);  // threads per combined slice
   const int KV = a.k / LPR;
 #define SELL_L(CC, LL, KK)                                                                                   \
   if (C == CC && LPR == LL && KV == KK) {                                                                   \
-    hipLaunchKernelGGL((dev::k_spmmv_rows<CC, LL, KK>), dim3(nb), dim3(64 * dev::kWavesPerBlock), 0, s, a); \
+    hipLaunchKernelGGL((dev::k_spmmv_rows<CC, LL, KK>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a); \
     hipError_t e_ = hipGetLastError();                                                                      \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                       \
     hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, 1), dim3(ncomb), 0, s, a);       \

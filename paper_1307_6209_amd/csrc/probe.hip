@@ -1,9 +1,12 @@
 // Bandwidth microbenchmarks that set the roofline bandwidth b of the
 // performance model (Sect. 2.1 of Kreutzer et al., arXiv:1307.6209): a
 // read-only sum over an array (the paper's "reduction" benchmark) and an
-// array copy, both with 16-byte non-temporal accesses; and a random-gather
+// array copy, both with 16-byte non-temporal accesses; a random-gather
 // rate (8-byte loads at hashed positions of an array), the ceiling of
-// products whose right-hand-side accesses have no locality.
+// products whose right-hand-side accesses have no locality; and a random-row
+// rate (whole rows of 128, 256 or 512 bytes at hashed row positions), the
+// same ceiling for the block form, whose k right-hand sides make each
+// access one row of 8k bytes.
 #include "sell_internal.h"
 
 namespace sell {
@@ -80,6 +83,31 @@ __global__ void __launch_bounds__(kBlock) k_gather(const double *__restrict__ a,
   if (threadIdx.x == 0 || s != s) sink[blockIdx.x] = s;
 }
 
+// Random rows of R = 16*LPR bytes: LPR lanes read one row (16 bytes each),
+// a wave 64/LPR rows per access; every lane keeps eight accesses in flight.
+// Row positions are hashed, so no index array is streamed. Plain (cached)
+// loads, as the block form's reads of X.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_rows(const d2 *__restrict__ a, uint32_t row_mask, int32_t per_lane,
+                                                 double *sink) {
+  constexpr int RPA = 64 / LPR;  // rows per access of a wave
+  const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const uint32_t g = (uint32_t)(lane / LPR), q = (uint32_t)(lane % LPR);
+  double s = 0.0;
+  for (int32_t i = 0; i < per_lane; i += 8) {
+    d2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t r = lowbias32((wave * (uint32_t)per_lane + (uint32_t)(i + u)) * RPA + g) & row_mask;
+      v[u] = a[(size_t)r * LPR + q];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u].x + v[u].y;
+  }
+  if (threadIdx.x == 0 || s != s) sink[blockIdx.x] = s;
+}
+
 }  // namespace
 
 constexpr int kProbeBlocks = 256 * 16;
@@ -102,6 +130,25 @@ int64_t probe_gather(const void *a, size_t bytes, double *sink, hipStream_t s, h
                      sink);
   *err = hipGetLastError();
   return (int64_t)kBlocks * kBlock * kPerLane;
+}
+
+int64_t probe_rows(const void *a, size_t bytes, int row_bytes, double *sink, hipStream_t s, hipError_t *err) {
+  const int lpr = row_bytes / (int)sizeof(d2);
+  uint32_t mask = 1;
+  while ((uint64_t)(mask + 1) * 2 * (uint64_t)row_bytes <= bytes && mask < 0x7fffffffu) mask = mask * 2 + 1;
+  constexpr int32_t kPerLane = 64;
+  constexpr int kBlocks = 2048;  // 8,192 waves x 64 accesses x 64/LPR rows
+  const dim3 grid(kBlocks), block(kBlock);
+  const d2 *p = static_cast<const d2 *>(a);
+  if (lpr == 8) hipLaunchKernelGGL(k_rows<8>, grid, block, 0, s, p, mask, kPerLane, sink);
+  else if (lpr == 16) hipLaunchKernelGGL(k_rows<16>, grid, block, 0, s, p, mask, kPerLane, sink);
+  else if (lpr == 32) hipLaunchKernelGGL(k_rows<32>, grid, block, 0, s, p, mask, kPerLane, sink);
+  else {
+    *err = hipErrorInvalidValue;
+    return 0;
+  }
+  *err = hipGetLastError();
+  return (int64_t)kBlocks * (kBlock / 64) * kPerLane * (64 / lpr);
 }
 
 hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s) {

@@ -34,7 +34,8 @@ struct SplitDesc {
   int64_t poff;
 };
 
-// Work unit of the batched kernel (adds the matrix index).
+// Work unit of the batched kernel (adds the matrix index; mat < 0: an empty
+// unit that only fills the grid).
 struct BUnit {
   int32_t mat;
   int32_t item;
@@ -63,6 +64,12 @@ inline Geom geom_of(int C, int V = 1) {
   g.wpc = C > 64 ? C / 64 : 1;
   return g;
 }
+
+// Waves per workgroup of the kernels that give each wave one work unit.
+constexpr int kWavesPerBlock = 4;
+// Accelerator dies (XCDs) of the device, each with its own L2; the hardware
+// dispatcher sends workgroup b of a launch to XCD b mod kXcds.
+constexpr int kXcds = 8;
 
 // Segments of split chunks are whole multiples of this many chunk columns,
 // so that every kernel's step width (at most 64 columns) divides them.
@@ -199,6 +206,10 @@ hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s);
 // Launches 2^27 random 8-byte gathers over the largest power-of-two prefix
 // of a (bytes); returns the gather count.
 int64_t probe_gather(const void *a, size_t bytes, double *sink, hipStream_t s, hipError_t *err);
+// Launches random whole-row reads (rows of row_bytes = 128, 256 or 512 bytes)
+// over the largest power-of-two number of rows that fits in bytes; returns
+// the row count.
+int64_t probe_rows(const void *a, size_t bytes, int row_bytes, double *sink, hipStream_t s, hipError_t *err);
 
 }  // namespace sell
 

@@ -137,7 +137,6 @@ __device__ __forceinline__ void opaque(T &v) {
   asm volatile("" : "+v"(v));
 }
 
-constexpr int kWavesPerBlock = 4;
 
 // One work unit: rows [h*rpw, (h+1)*rpw) of chunk `chunk`, chunk columns
 // [seg*seg_cols, ...) of it (all of them when nseg == 1).
@@ -536,6 +535,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
   }
   for (int64_t q = q0; q < q1; ++q) {
     const BUnit u = a.units[q];
+    if (u.mat < 0) continue;  // grid filler
     const BatchMat m = a.mats[u.mat];
     const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
     spmv_unit<COMBO, C, U, 1, true>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg,
