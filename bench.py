@@ -66,13 +66,59 @@ def kernel_source_hash() -> str:
 
 
 def stored_traffic(src_hash: str):
-    p = os.path.join(ROOT, "profiles", "traffic_stencil27_160_fp64.json")
+    p = TRAFFIC_FILE
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_hash") != src_hash:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil27_160_fp64.json")
+
+
+def store_traffic(fetch_db: str, write_db: str) -> dict:
+    """Host side: from the rocprofv3 databases of the two counter runs of
+    --pmc-pass (FETCH_SIZE, then WRITE_SIZE), the headline kernel's HBM
+    bytes per dispatch, each counter scaled by what it reads for the copy
+    probe of known size run in the same pass (512 MiB read and written), and
+    stored with the hash of the kernel sources they were taken on."""
+    import sqlite3
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        cols = [r[1] for r in con.execute("pragma table_info(counters_collection)")]
+        vals = {}
+        for row in con.execute("select * from counters_collection"):
+            d = dict(zip(cols, row))
+            if d["counter_name"] == counter:
+                vals.setdefault(d["kernel_name"], []).append(float(d["value"]))
+        return vals
+
+    fetch, write = per_kernel(fetch_db, "FETCH_SIZE"), per_kernel(write_db, "WRITE_SIZE")
+    prod = [k for k in fetch if k.startswith("void sell::dev::k_spmv")]
+    if not prod or not any("k_copy" in k for k in fetch):
+        raise SystemExit("store-traffic: no product or copy-probe dispatches in %s (run bench.py --pmc-pass)" % fetch_db)
+    head = max(prod, key=lambda k: len(fetch[k]))  # the 5 products of the pass
+    copy = [k for k in fetch if "k_copy" in k][0]
+    copy_bytes = 1 << 29  # half of the probe's 1 GiB is read, half written
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
+    ff = copy_bytes / (mean(fetch[copy]) * 1024.0)
+    wf = copy_bytes / (mean(write[copy]) * 1024.0)
+    fb, wb = mean(fetch[head]) * 1024.0 * ff, mean(write[head]) * 1024.0 * wf
+    out = {"kernel": head, "workload": "stencil27_160, SELL-32-1, FP64",
+           "command_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --pmc-pass",
+           "command_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -- python3 bench.py --pmc-pass",
+           "fetch_kib_per_dispatch": round(mean(fetch[head]), 1), "write_kib_per_dispatch": round(mean(write[head]), 1),
+           "copy_calibration": {"bytes_read_and_written": copy_bytes, "fetch_kib": round(mean(fetch[copy]), 1),
+                                "write_kib": round(mean(write[copy]), 1), "fetch_factor": round(ff, 4),
+                                "write_factor": round(wf, 4)},
+           "hbm_bytes_per_launch": int(round(fb + wb)), "kernel_source_hash": kernel_source_hash()}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
 
 
 def to_dev(A):
@@ -509,6 +555,8 @@ def main():
                     help="block form k = 16, 32, 64 on the power-law 1M matrix (with --pmc-pass: for counters)")
     ap.add_argument("--batch-pass", action="store_true",
                     help="batched launch over 64 power-law matrices (with --pmc-pass: for counters)")
+    ap.add_argument("--store-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="host only: write the headline's counter traffic from two --pmc-pass counter runs")
     ap.add_argument("--probe-sweep", action="store_true",
                     help="random-gather and random-row probes over array sizes 1 MiB .. 4 GiB, and the read probe")
     args = ap.parse_args()
@@ -516,6 +564,10 @@ def main():
         print("bench.py runs on one GPU only: the SELL-C-sigma product here is a single-device kernel "
               "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.store_traffic:
+        print(json.dumps(store_traffic(*args.store_traffic)))
+        return
 
     import torch
     import synth
