@@ -854,9 +854,24 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
         usplit.push_back(1);
       }
     }
+    // whole chunks; with C <= 32 each run of 64 / C consecutive chunks of
+    // width 0 or 1 is one unit (nseg 0: one wave covers all their rows)
+    const size_t grp = B->C <= 32 ? (size_t)(64 / B->C) : 0;
     for (size_t it = 0; it < s.cols.size(); ++it) {
       const int32_t w = s.cols[it];
       if (w > S) continue;
+      if (grp && w <= 1 && it + grp <= s.cols.size()) {
+        size_t e = it + 1;
+        while (e < it + grp && s.cols[e] <= 1) ++e;
+        if (e == it + grp) {
+          all.push_back({b, (int32_t)it, 0, 0, 0, {0, 0, 0}});
+          umat.push_back(b);
+          ucost.push_back(1 + kFixed);
+          usplit.push_back(0);
+          it = e - 1;
+          continue;
+        }
+      }
       all.push_back({b, (int32_t)it, 0, 1, 0, {0, 0, 0}});
       umat.push_back(b);
       ucost.push_back((w + g.T - 1) / g.T + kFixed);
@@ -872,12 +887,13 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
   int64_t nwaves = 0;
   if (persistent) {
     const int wpcu = std::max(1, sell::batch_waves_per_cu(B->combo, B->C, B->U));
-    const int64_t per_round = (int64_t)sell::kWavesPerBlock * sell::kXcds;
+    const int64_t per_round = (int64_t)sell::kBatchPersistentWaves * sell::kXcds;
     nwaves = std::min<int64_t>((int64_t)di.cus * wpcu, (int64_t)all.size());
     nwaves = std::max<int64_t>(per_round, (nwaves + per_round - 1) / per_round * per_round);
   }
-  const sell::XcdPlan plan =
-      sell::plan_xcd(umat, ucost, usplit, count, sell::kWavesPerBlock, sell::kXcds, nwaves);
+  const sell::XcdPlan plan = sell::plan_xcd(umat, ucost, usplit, count,
+                                            persistent ? sell::kBatchPersistentWaves : sell::kWavesPerBlock,
+                                            sell::kXcds, nwaves);
   std::vector<sell::BUnit> units(plan.order.size());
   for (size_t i = 0; i < plan.order.size(); ++i)
     units[i] = plan.order[i] < 0 ? sell::BUnit{-1, 0, 0, 1, 0, {0, 0, 0}} : all[(size_t)plan.order[i]];

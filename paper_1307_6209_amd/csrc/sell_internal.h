@@ -67,6 +67,10 @@ inline Geom geom_of(int C, int V = 1) {
 
 // Waves per workgroup of the kernels that give each wave one work unit.
 constexpr int kWavesPerBlock = 4;
+// Waves per workgroup of the persistent batched kernel: one (its waves run
+// slices of different lengths; a workgroup holds its CU slots until its
+// last wave ends).
+constexpr int kBatchPersistentWaves = 1;
 // Accelerator dies (XCDs) of the device, each with its own L2; the hardware
 // dispatcher sends workgroup b of a launch to XCD b mod kXcds.
 constexpr int kXcds = 8;
@@ -165,7 +169,7 @@ hipError_t launch_spmmv_rows(int C, int LPR, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmv_xw(int combo, int C, int V, int U, const SpmvArgs &a, const XwArgs &w, size_t lds_bytes,
                           hipStream_t s);
 hipError_t launch_batch(int combo, int C, int U, const BatchArgs &a, hipStream_t s);
-// Resident waves per CU of the batched kernel (persistent grid size).
+// Resident waves per CU of the persistent batched kernel (its grid size).
 int batch_waves_per_cu(int combo, int C, int U);
 
 // Build kernels.

@@ -515,6 +515,37 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
                                  a.partial, a.seg_cols, lane);
 }
 
+// A group of 64 / C consecutive chunks of width 0 or 1 (C <= 32) as one
+// work unit of the batched kernel: their slots are consecutive (C per chunk
+// of width 1), so one wave covers all their rows, lane l holding row l % C
+// of chunk item + l / C -- one product per row, no cross-lane sum; slots
+// holding 0 skip the gather. The result equals spmv_unit's for these chunks
+// bit for bit (there the lanes past the chunk's one column add +0 to each
+// row's product; here +0 is added once).
+template <int COMBO, int C>
+__device__ __forceinline__ void spmv_group_w1(const void *__restrict__ valv, const int32_t *__restrict__ col,
+                                              const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
+                                              const int32_t *__restrict__ perm, const void *__restrict__ xv,
+                                              void *__restrict__ yv, int64_t nrows, int32_t item, int lane) {
+  using V = typename Types<COMBO>::V;
+  using X = typename Types<COMBO>::X;
+  using A = typename Types<COMBO>::A;
+  static_assert(C <= 32, "at least two chunks per wave");
+  const int32_t c = item + lane / C;
+  const int r = lane % C;
+  const int64_t p = (int64_t)c * C + r;
+  const int w = clp[c];
+  const int64_t sl = cs[c] + r;
+  A acc = 0;
+  if (w > 0) {
+    const V v = __builtin_nontemporal_load(static_cast<const V *>(valv) + sl);
+    const int32_t ci = __builtin_nontemporal_load(col + sl);
+    if (v != 0) acc = fmac(cvt(v), static_cast<const X *>(xv)[ci], (A)0);
+  }
+  acc += (A)0;
+  if (p < nrows) __builtin_nontemporal_store(acc, static_cast<A *>(yv) + (perm ? (int64_t)perm[p] : p));
+}
+
 // Batched form: one launch over the concatenated work units of all
 // matrices. Default: one unit per wave (the hardware dispatcher balances the
 // uneven matrices). Persistent form (slice != nullptr): a grid of resident
@@ -525,7 +556,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
   // the wave index is uniform over the wave: the unit and matrix
   // descriptors are then read through the scalar cache (94 -> 70 VGPRs at
   // C = 32, eight slots in flight)
-  const int64_t w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   int64_t q0, q1;
   if (a.slice) {
     if (w >= a.nwaves) return;
@@ -540,6 +571,12 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
     const BUnit u = a.units[q];
     if (u.mat < 0) continue;  // grid filler
     const BatchMat m = a.mats[u.mat];
+    if constexpr (C <= 32) {
+      if (u.nseg == 0) {  // a group of chunks of width 0 or 1
+        spmv_group_w1<COMBO, C>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, lane);
+        continue;
+      }
+    }
     const int64_t poff = u.nseg > 1 ? a.splits[u.sid].poff : 0;
     spmv_unit<COMBO, C, U, 1, true>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, u.seg, u.nseg,
                                     poff, a.partial, a.seg_cols, lane);
@@ -915,10 +952,11 @@ template <int COMBO>
 hipError_t launch_batch_t(int C, int U, const BatchArgs &a, hipStream_t s) {
   if (a.nunits <= 0) return hipSuccess;
   const int64_t waves = a.slice ? a.nwaves : a.nunits;
-  const unsigned nb = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  const int wpb = a.slice ? kBatchPersistentWaves : kWavesPerBlock;
+  const unsigned nb = (unsigned)((waves + wpb - 1) / wpb);
 #define SELL_L(CC, UU)                                                                                     \
   if (C == CC && U == UU) {                                                                               \
-    hipLaunchKernelGGL((k_batch<COMBO, CC, UU>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a);           \
+    hipLaunchKernelGGL((k_batch<COMBO, CC, UU>), dim3(nb), dim3(64 * wpb), 0, s, a);           \
     hipError_t e_ = hipGetLastError();                                                                    \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                     \
     const unsigned nbc = (unsigned)((a.nsplit + kWavesPerBlock - 1) / kWavesPerBlock);                     \
@@ -935,10 +973,10 @@ int batch_waves_per_cu_t(int C, int U) {
   int blocks = 0;
 #define SELL_L(CC, UU)                                                                                              \
   if (C == CC && U == UU) {                                                                                        \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<COMBO, CC, UU>, 64 * kWavesPerBlock, 0) != \
-        hipSuccess)                                                                                                \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<COMBO, CC, UU>, 64 * kBatchPersistentWaves,  \
+                                                     0) != hipSuccess)                                             \
       blocks = 1;                                                                                                  \
-    return blocks * kWavesPerBlock;                                                                                \
+    return blocks * kBatchPersistentWaves;                                                                                \
   }
   SELL_FOR_EACH_CU(SELL_L)
 #undef SELL_L
