@@ -382,6 +382,37 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
     SELL_HIP(hipMemcpyAsync(h->units, units.data(), sizeof(sell::Unit) * units.size(), hipMemcpyHostToDevice, s));
     SELL_HIP(hipMemcpyAsync(h->splits, splits.data(), sizeof(sell::SplitDesc) * splits.size(),
                             hipMemcpyHostToDevice, s));
+    // the single-vector product's list: runs of 64 / C whole chunks of width
+    // 0 or 1 become one unit each (one wave covers all their rows)
+    if (C <= 32) {
+      const size_t grp = (size_t)(64 / C);
+      size_t nwhole = 0;
+      for (int64_t it = 0; it < h->nitems; ++it) nwhole += st.cols[(size_t)it] <= S;
+      std::vector<sell::Unit> u1(units.begin(), units.end() - (ptrdiff_t)nwhole);  // the split segments
+      int64_t ngroups = 0;
+      for (size_t it = 0; it < (size_t)h->nitems; ++it) {
+        const int32_t w = st.cols[it];
+        if (w > S) continue;
+        if (w <= 1 && it + grp <= (size_t)h->nitems) {
+          size_t e = it + 1;
+          while (e < it + grp && st.cols[e] <= 1) ++e;
+          if (e == it + grp) {
+            u1.push_back({(int32_t)it, 0, 0, 0});
+            ++ngroups;
+            it = e - 1;
+            continue;
+          }
+        }
+        u1.push_back({(int32_t)it, 0, 1, 0});
+      }
+      if (ngroups > 0) {
+        h->units1 = static_cast<sell::Unit *>(owned_alloc(h.get(), mem, sizeof(sell::Unit) * u1.size()));
+        if (!h->units1) return fail(SELL_ERR_OOM, "sell_build: work plan");
+        h->nunits1 = (int64_t)u1.size();
+        SELL_HIP(hipMemcpyAsync(h->units1, u1.data(), sizeof(sell::Unit) * u1.size(), hipMemcpyHostToDevice, s));
+        SELL_HIP(hipStreamSynchronize(s));  // u1 ends with this scope
+      }
+    }
     SELL_HIP(hipStreamSynchronize(s));
   } else {
     h->nunits = h->nitems;
@@ -503,6 +534,10 @@ sell_status spmv_run(sell_handle h, const void *x, void *y, void *stream, void *
   if (h->nrows == 0) return SELL_OK;
   sell::SpmvArgs a = args_of(h, x, y);
   if (partial) a.partial = partial;
+  if (h->units1) {  // whole chunks of width 0 or 1 grouped 64 / C per wave
+    a.units = h->units1;
+    a.nwork = h->nunits1;
+  }
   // padding-heavy layouts skip the gathers of their zero slots; near-dense
   // chunks skip the per-slot test
   const bool skip_zero = h->beta < 0.9;

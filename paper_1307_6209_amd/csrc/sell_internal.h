@@ -244,6 +244,10 @@ struct sell_matrix {
   int64_t nitems = 0;
   int64_t nunits = 0;
   sell::Unit *units = nullptr;  // nullptr when no chunk is split
+  // the single-vector product's units: the same, with each run of 64 / C
+  // chunks of width 0 or 1 as one unit (nseg 0; C <= 32); nullptr: units
+  sell::Unit *units1 = nullptr;
+  int64_t nunits1 = 0;
   int64_t nsplit = 0;
   int64_t nsegs = 0;                  // total segments of split items
   sell::SplitDesc *splits = nullptr;  // per split id

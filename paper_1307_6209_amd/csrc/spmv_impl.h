@@ -495,28 +495,8 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_combine(SpmvArgs a) {
   combine_split<COMBO, C>(a.splits[w], a.perm, a.partial, a.y, a.nrows, threadIdx.x & 63);
 }
 
-template <int COMBO, int C, int U, int VV, bool ZS>
-__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (w >= a.nwork) return;
-  int32_t item, seg = 0, nseg = 1;
-  int64_t poff = 0;
-  if (a.units) {
-    const Unit u = a.units[w];
-    item = u.item;
-    seg = u.seg;
-    nseg = u.nseg;
-    if (nseg > 1) poff = a.splits[u.sid].poff;
-  } else {
-    item = (int32_t)w;
-  }
-  spmv_unit<COMBO, C, U, VV, ZS>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff,
-                                 a.partial, a.seg_cols, lane);
-}
-
 // A group of 64 / C consecutive chunks of width 0 or 1 (C <= 32) as one
-// work unit of the batched kernel: their slots are consecutive (C per chunk
+// work unit of the single-vector and batched kernels: their slots are consecutive (C per chunk
 // of width 1), so one wave covers all their rows, lane l holding row l % C
 // of chunk item + l / C -- one product per row, no cross-lane sum; slots
 // holding 0 skip the gather. The result equals spmv_unit's for these chunks
@@ -544,6 +524,32 @@ __device__ __forceinline__ void spmv_group_w1(const void *__restrict__ valv, con
   }
   acc += (A)0;
   if (p < nrows) __builtin_nontemporal_store(acc, static_cast<A *>(yv) + (perm ? (int64_t)perm[p] : p));
+}
+
+template <int COMBO, int C, int U, int VV, bool ZS>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w >= a.nwork) return;
+  int32_t item, seg = 0, nseg = 1;
+  int64_t poff = 0;
+  if (a.units) {
+    const Unit u = a.units[w];
+    item = u.item;
+    seg = u.seg;
+    nseg = u.nseg;
+    if (nseg > 1) poff = a.splits[u.sid].poff;
+    if constexpr (C <= 32) {
+      if (nseg == 0) {  // a group of chunks of width 0 or 1
+        spmv_group_w1<COMBO, C>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, lane);
+        return;
+      }
+    }
+  } else {
+    item = (int32_t)w;
+  }
+  spmv_unit<COMBO, C, U, VV, ZS>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff,
+                                 a.partial, a.seg_cols, lane);
 }
 
 // Batched form: one launch over the concatenated work units of all
