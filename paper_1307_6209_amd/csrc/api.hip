@@ -382,10 +382,11 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
     SELL_HIP(hipMemcpyAsync(h->units, units.data(), sizeof(sell::Unit) * units.size(), hipMemcpyHostToDevice, s));
     SELL_HIP(hipMemcpyAsync(h->splits, splits.data(), sizeof(sell::SplitDesc) * splits.size(),
                             hipMemcpyHostToDevice, s));
-    // the single-vector product's list: runs of 64 / C whole chunks of width
-    // 0 or 1 become one unit each (one wave covers all their rows)
-    if (C <= 32) {
+    // the single-vector product's list: runs of 64 / C whole chunks at most
+    // 64 / C columns wide become one unit each (one wave covers all their rows)
+    if (C >= 8 && C <= 32) {
       const size_t grp = (size_t)(64 / C);
+      const int32_t wmax = 64 / C;
       size_t nwhole = 0;
       for (int64_t it = 0; it < h->nitems; ++it) nwhole += st.cols[(size_t)it] <= S;
       std::vector<sell::Unit> u1(units.begin(), units.end() - (ptrdiff_t)nwhole);  // the split segments
@@ -393,9 +394,9 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
       for (size_t it = 0; it < (size_t)h->nitems; ++it) {
         const int32_t w = st.cols[it];
         if (w > S) continue;
-        if (w <= 1 && it + grp <= (size_t)h->nitems) {
+        if (w <= wmax && it + grp <= (size_t)h->nitems) {
           size_t e = it + 1;
-          while (e < it + grp && st.cols[e] <= 1) ++e;
+          while (e < it + grp && st.cols[e] <= wmax) ++e;
           if (e == it + grp) {
             u1.push_back({(int32_t)it, 0, 0, 0});
             ++ngroups;
@@ -889,15 +890,17 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
         usplit.push_back(1);
       }
     }
-    // whole chunks; with C <= 32 each run of 64 / C consecutive chunks of
-    // width 0 or 1 is one unit (nseg 0: one wave covers all their rows)
-    const size_t grp = B->C <= 32 ? (size_t)(64 / B->C) : 0;
+    // whole chunks; with C in 8..32 each run of 64 / C consecutive chunks at
+    // most 64 / C columns wide is one unit (nseg 0: one wave covers all their
+    // rows)
+    const size_t grp = B->C >= 8 && B->C <= 32 ? (size_t)(64 / B->C) : 0;
+    const int32_t wmax = (int32_t)grp;
     for (size_t it = 0; it < s.cols.size(); ++it) {
       const int32_t w = s.cols[it];
       if (w > S) continue;
-      if (grp && w <= 1 && it + grp <= s.cols.size()) {
+      if (grp && w <= wmax && it + grp <= s.cols.size()) {
         size_t e = it + 1;
-        while (e < it + grp && s.cols[e] <= 1) ++e;
+        while (e < it + grp && s.cols[e] <= wmax) ++e;
         if (e == it + grp) {
           all.push_back({b, (int32_t)it, 0, 0, 0, {0, 0, 0}});
           umat.push_back(b);

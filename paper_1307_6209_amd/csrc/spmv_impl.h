@@ -495,35 +495,48 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_combine(SpmvArgs a) {
   combine_split<COMBO, C>(a.splits[w], a.perm, a.partial, a.y, a.nrows, threadIdx.x & 63);
 }
 
-// A group of 64 / C consecutive chunks of width 0 or 1 (C <= 32) as one
-// work unit of the single-vector and batched kernels: their slots are consecutive (C per chunk
-// of width 1), so one wave covers all their rows, lane l holding row l % C
-// of chunk item + l / C -- one product per row, no cross-lane sum; slots
-// holding 0 skip the gather. The result equals spmv_unit's for these chunks
-// bit for bit (there the lanes past the chunk's one column add +0 to each
-// row's product; here +0 is added once).
+// A group of G = 64 / C consecutive chunks (C in 8..32), each at most
+// T = 64 / C columns wide -- one wave step of the one-slot-per-lane kernel --
+// as one work unit: one wave covers all their rows, lane l holding row l % C
+// of chunk item + l / C and its (at most T) products. The products are
+// added as the T lanes of a row add them in spmv_unit with one slot per lane
+// (a butterfly over lane offsets 32, 16, ..., C with the missing columns as
+// +0), so the result is the same bit for bit; slots holding 0 skip the
+// gather.
 template <int COMBO, int C>
-__device__ __forceinline__ void spmv_group_w1(const void *__restrict__ valv, const int32_t *__restrict__ col,
-                                              const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
-                                              const int32_t *__restrict__ perm, const void *__restrict__ xv,
-                                              void *__restrict__ yv, int64_t nrows, int32_t item, int lane) {
+__device__ __forceinline__ void spmv_group(const void *__restrict__ valv, const int32_t *__restrict__ col,
+                                           const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
+                                           const int32_t *__restrict__ perm, const void *__restrict__ xv,
+                                           void *__restrict__ yv, int64_t nrows, int32_t item, int lane) {
   using V = typename Types<COMBO>::V;
   using X = typename Types<COMBO>::X;
   using A = typename Types<COMBO>::A;
-  static_assert(C <= 32, "at least two chunks per wave");
+  constexpr int T = 64 / C;
+  static_assert(C >= 8 && C <= 32, "two to eight chunks per wave");
   const int32_t c = item + lane / C;
   const int r = lane % C;
   const int64_t p = (int64_t)c * C + r;
   const int w = clp[c];
-  const int64_t sl = cs[c] + r;
-  A acc = 0;
-  if (w > 0) {
-    const V v = __builtin_nontemporal_load(static_cast<const V *>(valv) + sl);
-    const int32_t ci = __builtin_nontemporal_load(col + sl);
-    if (v != 0) acc = fmac(cvt(v), static_cast<const X *>(xv)[ci], (A)0);
+  const int64_t base = cs[c] + r;
+  V v[T];
+  int32_t ci[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    v[j] = 0;
+    ci[j] = 0;
+    if (j < w) {
+      v[j] = __builtin_nontemporal_load(static_cast<const V *>(valv) + base + (int64_t)j * C);
+      ci[j] = __builtin_nontemporal_load(col + base + (int64_t)j * C);
+    }
   }
-  acc += (A)0;
-  if (p < nrows) __builtin_nontemporal_store(acc, static_cast<A *>(yv) + (perm ? (int64_t)perm[p] : p));
+  A s[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) s[j] = v[j] != 0 ? fmac(cvt(v[j]), static_cast<const X *>(xv)[ci[j]], (A)0) : (A)0;
+#pragma unroll
+  for (int d = T / 2; d >= 1; d >>= 1)
+#pragma unroll
+    for (int t = 0; t < d; ++t) s[t] = s[t] + s[t + d];
+  if (p < nrows) __builtin_nontemporal_store(s[0], static_cast<A *>(yv) + (perm ? (int64_t)perm[p] : p));
 }
 
 template <int COMBO, int C, int U, int VV, bool ZS>
@@ -539,9 +552,9 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
     seg = u.seg;
     nseg = u.nseg;
     if (nseg > 1) poff = a.splits[u.sid].poff;
-    if constexpr (C <= 32) {
-      if (nseg == 0) {  // a group of chunks of width 0 or 1
-        spmv_group_w1<COMBO, C>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, lane);
+    if constexpr (C >= 8 && C <= 32) {
+      if (nseg == 0) {  // a group of short chunks
+        spmv_group<COMBO, C>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, lane);
         return;
       }
     }
@@ -577,9 +590,9 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_batch(BatchArgs a) {
     const BUnit u = a.units[q];
     if (u.mat < 0) continue;  // grid filler
     const BatchMat m = a.mats[u.mat];
-    if constexpr (C <= 32) {
-      if (u.nseg == 0) {  // a group of chunks of width 0 or 1
-        spmv_group_w1<COMBO, C>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, lane);
+    if constexpr (C >= 8 && C <= 32) {
+      if (u.nseg == 0) {  // a group of short chunks
+        spmv_group<COMBO, C>(m.val, m.col, m.cs, m.cl, m.perm, m.x, m.y, m.nrows, u.item, lane);
         continue;
       }
     }

@@ -45,6 +45,7 @@ def test_batch_fp64(C, form):
     xs = [synth.uniform(A.ncols, 50 + i, 1) for i, A in enumerate(mats)]
     say("batch C", C, "rows", sum(A.nrows for A in mats))
     ys = run(b, mats, xs, (torch.float64, torch.float64))
+    short = wide = False
     for A, h, x, y in zip(mats, hs, xs, ys):
         check_fp64(A, y, x, m=batch_chain_per_row(A, h, C))
     # a second call with new vectors (the pointer table is rewritten)
@@ -168,7 +169,9 @@ def short_rows(n, m, seed):
     """Rows of length 0 or 1 and a few longer ones (values U[-1,1))."""
     rng = np.random.default_rng(seed)
     lens = (rng.random(n) >= 0.3).astype(np.int64)
-    lens[rng.integers(0, n, max(1, n // 500))] = 5
+    lens[rng.random(n) < 0.2] = 2
+    lens[rng.random(n) < 0.05] = 3
+    lens[rng.integers(0, n, max(1, n // 500))] = 9
     rpt = np.zeros(n + 1, np.int64)
     np.cumsum(lens, out=rpt[1:])
     col = np.concatenate([np.sort(rng.choice(m, int(L), replace=False)) for L in lens if L] or
@@ -179,17 +182,20 @@ def short_rows(n, m, seed):
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("C", [16, 32])
 def test_batch_width1_groups(form, C):
-    """Chunks of width 0 or 1 run 64 / C to a wave in the batched kernel: the
-    rows of those chunks equal the single-matrix product bit for bit (one
-    product per row in both), every row is within the oracle's bound, and
-    the ragged ends (matrix sizes not multiples of the group) are covered."""
+    """Chunks of at most 64 / C columns run 64 / C to a wave in the batched
+    kernel (and in the single-vector product on split layouts): every row
+    equals the single-matrix product with one slot per lane bit for bit (the
+    same products, added in the same tree), is within the oracle's bound,
+    and the ragged ends (matrix sizes not multiples of the group) are
+    covered."""
     import torch
     from paper_1307_6209_amd import sellcs
     mats = [short_rows(n, 3000 + 7 * n % 977, 70 + i) for i, n in enumerate((997, 4096, 1, 77, 12_345, 64))]
-    hs = [build(A, C, 10**9) for A in mats]
+    hs = [build(A, C, 10**9, vec=1) for A in mats]
     b = create(form, hs)
     xs = [synth.uniform(A.ncols, 90 + i, 1) for i, A in enumerate(mats)]
     ys = run(b, mats, xs, (torch.float64, torch.float64))
+    short = wide = False
     for A, h, x, y in zip(mats, hs, xs, ys):
         check_fp64(A, y, x, m=batch_chain_per_row(A, h, C))
         lay = sellcs.sell_export(h, parts=("perm", "cl"))
@@ -198,7 +204,8 @@ def test_batch_width1_groups(form, C):
         single = torch.full((A.nrows,), float("nan"), dtype=torch.float64, device="cuda")
         sellcs.sell_spmv(h, torch.from_numpy(x).cuda(), single)
         torch.cuda.synchronize()
-        s = single.cpu().numpy()
-        one = w <= 1
-        assert np.array_equal(y[one].view(np.uint64), s[one].view(np.uint64))
+        assert np.array_equal(y.view(np.uint64), single.cpu().numpy().view(np.uint64))
+        short |= bool(((w > 1) & (w <= 64 // C)).any())
+        wide |= bool((w > 64 // C).any())
+    assert short and wide
     b.close()
