@@ -637,7 +637,8 @@ def main():
     sizes_alg = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1)
     alg = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes_alg)
     sizes = model.sizes_for("f64", "f64", HEADLINE["sigma"] > 1, xwindow=inf["xwindow"] == 1,
-                            segments_per_chunk=inf["xsegments"] / max(1, inf["nchunks"]))
+                            segments_per_chunk=inf["xsegments"] / max(1, inf["nchunks"]),
+                            group_chunks=max(1, inf["xwindow_group_chunks"]))
     moved = model.algorithmic_bytes(A.nrows, A.ncols, inf["padded"], inf["nchunks"], 1, sizes)
     achieved = alg / sec * 1e-9
     achieved_moved = moved / sec * 1e-9
@@ -662,6 +663,7 @@ def main():
                    "padded_slots": inf["padded"],
                    "index": "uint16 window positions (x window staged in LDS)" if inf["xwindow"] else "int32",
                    "x_window_segments": inf["xsegments"], "x_window_max_elements": inf["xwindow_max"],
+                   "x_window_group_chunks": inf["xwindow_group_chunks"],
                    "values": "f64", "x": "f64", "y": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,

@@ -96,19 +96,22 @@ typedef struct {
                            paper recommends for iterative solvers (Sect. 3.4);
                            see sell_permute / sell_unpermute */
   int32_t xwindow;      /* x window in LDS for sell_spmv: the distinct columns of
-                           each group of 4 chunks (one workgroup) are staged in
-                           LDS once and the slots also store their 16-bit
-                           position in it (2 bytes streamed instead of 4, x read
-                           from LDS; same result bit for bit). 0: used when it
-                           fits and the matrix has at least two groups per
-                           compute unit (C in 8..64, vec 1 or 2, no split chunks, at most
-                           8192 slots and 1024 runs of consecutive columns per
-                           group, window <= 16 KiB); -1: never;
-                           1: required (SELL_ERR_UNSUPPORTED when it cannot be
-                           built, window up to 64 KiB). The global column
-                           indices are kept for sell_export, sell_spmmv and the
-                           batch. */
+                           each group of G consecutive chunks (one workgroup, one
+                           wave per chunk) are staged in LDS once and the slots
+                           also store their 16-bit position in it (2 bytes
+                           streamed instead of 4, x read from LDS; same result
+                           bit for bit). 0: used when it fits and the matrix has
+                           at least two groups of 4 chunks per compute unit (C in
+                           8..64, vec 1 or 2, no split chunks, at most 8192
+                           slots and 1024 runs of consecutive columns per group,
+                           window <= 4 KiB times G); -1: never; 1: required
+                           (SELL_ERR_UNSUPPORTED when it cannot be built, window
+                           up to 16 KiB times G). The global column indices are
+                           kept for sell_export, sell_spmmv and the batch. */
   const sell_allocator *alloc; /* NULL: hipMalloc/hipFree */
+  int32_t xwindow_chunks; /* G, chunks per x-window group: 0 auto (8 at C = 32
+                           when those windows fit and leave two groups per
+                           compute unit, else 4), or 4 or 8 (that size only) */
 } sell_build_opts;
 
 typedef struct {
@@ -133,7 +136,7 @@ typedef struct {
   int32_t xwindow;       /* 1 when sell_spmv stages x windows in LDS */
   int32_t xwindow_max;   /* largest window, in x elements */
   int64_t xsegments;     /* runs of consecutive columns over all windows */
-  int32_t xwindow_group_chunks; /* chunks that share one x window (a workgroup) */
+  int32_t xwindow_group_chunks; /* chunks that share one x window (a workgroup): 4 or 8; 0 without window */
 } sell_info_t;
 
 /*

@@ -70,10 +70,10 @@ DeviceInfo device_info() {
   return d;
 }
 
-// Dynamic LDS of the x-window product: the window, then the segment table
-// with room for one entry per thread.
-size_t xw_lds_bytes(int64_t maxwin, int64_t maxseg, size_t xsz) {
-  return (((size_t)maxwin * xsz + 7) & ~(size_t)7) + 8 * (size_t)std::max<int64_t>(maxseg, 64 * sell::kXwChunks);
+// Dynamic LDS of the x-window product with gc chunks (waves) per workgroup:
+// the window, then the segment table with room for one entry per thread.
+size_t xw_lds_bytes(int64_t maxwin, int64_t maxseg, size_t xsz, int gc) {
+  return (((size_t)maxwin * xsz + 7) & ~(size_t)7) + 8 * (size_t)std::max<int64_t>(maxseg, 64 * (int64_t)gc);
 }
 
 // Device memory through the caller's allocator or hipMalloc.
@@ -225,6 +225,8 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
   if (o.alloc && (!o.alloc->alloc || !o.alloc->free))
     return fail(SELL_ERR_INVALID_ARG, "sell_build: allocator needs alloc and free");
   if (o.xwindow < -1 || o.xwindow > 1) return fail(SELL_ERR_INVALID_ARG, "sell_build: xwindow must be -1, 0 or 1");
+  if (o.xwindow_chunks != 0 && o.xwindow_chunks != sell::kXwChunks && o.xwindow_chunks != sell::kXwChunksWide)
+    return fail(SELL_ERR_INVALID_ARG, "sell_build: xwindow_chunks must be 0, 4 or 8");
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::unique_ptr<sell_matrix> h(new sell_matrix());
@@ -432,7 +434,13 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
       if (o.xwindow == 1)
         return fail(SELL_ERR_UNSUPPORTED, "sell_build: the x window needs C in 8..64, vec 1 or 2 and no split chunks");
     } else {
-      const int64_t ngroups = (nc + sell::kXwChunks - 1) / sell::kXwChunks;
+      // at C = 32, groups of kXwChunksWide chunks when their windows fit
+      // (fewer workgroups stage the x lines that neighbouring chunks share;
+      // measured on the 27-point stencil, 160^3: FP64 +1 %, FP32 +3 to 6 %,
+      // BF16 +5 to 8 %), else of kXwChunks (at C = 16 the wide groups ran
+      // 4 to 15 % slower, at C = 64 they exceed the slot limit of a group
+      // and, with a limit twice as large, ran no faster); an explicit
+      // xwindow_chunks builds that size only
       struct XwSmall {
         uint32_t flags;
         int32_t maxwin;
@@ -440,26 +448,44 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
         int32_t pad;
         int64_t nseg;
       };
-      XwSmall *dxs = static_cast<XwSmall *>(tmp.get(sizeof(XwSmall)));
-      int64_t *cnt = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)(ngroups + 1)));
-      int64_t *offs = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)(ngroups + 1)));
-      int64_t *stmp = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)sell::scan_tmp_elems(ngroups + 1)));
-      if (!dxs || !cnt || !offs || !stmp) return fail(SELL_ERR_OOM, "sell_build: x window temporaries");
-      SELL_HIP(hipMemsetAsync(dxs, 0, sizeof(XwSmall), s));
-      SELL_HIP(sell::build_xw_count(h->col, h->cs, nc, cnt, &dxs->flags, &dxs->maxwin, &dxs->maxseg, s));
-      SELL_HIP(sell::build_scan(cnt, offs, ngroups + 1, stmp, s));
-      SELL_HIP(hipMemcpyAsync(&dxs->nseg, offs + ngroups, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-      XwSmall xs{};
-      SELL_HIP(hipMemcpyAsync(&xs, dxs, sizeof(XwSmall), hipMemcpyDeviceToHost, s));
-      SELL_HIP(hipStreamSynchronize(s));
       const size_t xsz = h->xdt == SELL_F64 ? 8 : 4;
-      const size_t budget = o.xwindow == 1 ? (size_t)64 << 10 : (size_t)16 << 10;
-      if (xs.flags || (size_t)xs.maxwin * xsz > budget || xs.maxseg > sell::kXwMaxSeg ||
-          xw_lds_bytes(xs.maxwin, xs.maxseg, xsz) > di.lds_per_block) {
+      XwSmall *dxs = static_cast<XwSmall *>(tmp.get(sizeof(XwSmall)));
+      const int64_t ngroups_max = (nc + sell::kXwChunks - 1) / sell::kXwChunks;
+      int64_t *cnt = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)(ngroups_max + 1)));
+      int64_t *offs = static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)(ngroups_max + 1)));
+      int64_t *stmp =
+          static_cast<int64_t *>(tmp.get(sizeof(int64_t) * (size_t)sell::scan_tmp_elems(ngroups_max + 1)));
+      if (!dxs || !cnt || !offs || !stmp) return fail(SELL_ERR_OOM, "sell_build: x window temporaries");
+      int gcs[2] = {sell::kXwChunksWide, sell::kXwChunks};
+      int ngc = 2;
+      if (o.xwindow_chunks != 0) {
+        gcs[0] = o.xwindow_chunks;
+        ngc = 1;
+      }
+      XwSmall xs{};
+      int gc = 0;
+      int64_t ngroups = 0;
+      for (int i = 0; i < ngc && gc == 0; ++i) {
+        ngroups = (nc + gcs[i] - 1) / gcs[i];
+        // the automatic choice keeps two workgroups per compute unit
+        if (ngc > 1 && i + 1 < ngc && (C != 32 || (o.xwindow != 1 && ngroups < 2 * (int64_t)di.cus))) continue;
+        SELL_HIP(hipMemsetAsync(dxs, 0, sizeof(XwSmall), s));
+        SELL_HIP(sell::build_xw_count(h->col, h->cs, nc, gcs[i], cnt, &dxs->flags, &dxs->maxwin, &dxs->maxseg, s));
+        SELL_HIP(sell::build_scan(cnt, offs, ngroups + 1, stmp, s));
+        SELL_HIP(hipMemcpyAsync(&dxs->nseg, offs + ngroups, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+        SELL_HIP(hipMemcpyAsync(&xs, dxs, sizeof(XwSmall), hipMemcpyDeviceToHost, s));
+        SELL_HIP(hipStreamSynchronize(s));
+        // window budget per wave of the workgroup: 4 KiB (16 KiB when required)
+        const size_t budget = (o.xwindow == 1 ? (size_t)16 << 10 : (size_t)4 << 10) * (size_t)gcs[i];
+        if (!xs.flags && (size_t)xs.maxwin * xsz <= budget && xs.maxseg <= sell::kXwMaxSeg &&
+            xw_lds_bytes(xs.maxwin, xs.maxseg, xsz, gcs[i]) <= di.lds_per_block)
+          gc = gcs[i];
+      }
+      if (gc == 0) {
         if (o.xwindow == 1)
           return fail(SELL_ERR_UNSUPPORTED,
                       "sell_build: x window too large (more than 8192 slots or 1024 column runs per group, "
-                      "window over 64 KiB, or more LDS than a workgroup may use)");
+                      "window over 16 KiB per chunk of the group, or more LDS than a workgroup may use)");
       } else {
         h->xsegoff = static_cast<int64_t *>(owned_alloc(h.get(), mem, sizeof(int64_t) * (size_t)(ngroups + 1)));
         h->xseg = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * 3 * (size_t)xs.nseg));
@@ -467,8 +493,9 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
         if (!h->xsegoff || !h->xseg || !h->lcol) return fail(SELL_ERR_OOM, "sell_build: x window arrays");
         SELL_HIP(hipMemcpyAsync(h->xsegoff, offs, sizeof(int64_t) * (size_t)(ngroups + 1), hipMemcpyDeviceToDevice,
                                 s));
-        SELL_HIP(sell::build_xw_fill(h->col, h->cs, nc, h->xsegoff, h->xseg, h->lcol, s));
+        SELL_HIP(sell::build_xw_fill(h->col, h->cs, nc, gc, h->xsegoff, h->xseg, h->lcol, s));
         SELL_HIP(hipStreamSynchronize(s));
+        h->xw_gc = gc;
         h->nxseg = xs.nseg;
         h->xwin_max = xs.maxwin;
         h->xseg_max = xs.maxseg;
@@ -544,8 +571,8 @@ sell_status spmv_run(sell_handle h, const void *x, void *y, void *stream, void *
   const bool skip_zero = h->beta < 0.9;
   hipError_t e;
   if (h->lcol) {  // x windows staged in LDS
-    const sell::XwArgs w{h->lcol, h->xsegoff, h->xseg, h->xwin_max};
-    const size_t lds = xw_lds_bytes(h->xwin_max, h->xseg_max, h->xdt == SELL_F64 ? 8 : 4);
+    const sell::XwArgs w{h->lcol, h->xsegoff, h->xseg, h->xwin_max, h->xw_gc};
+    const size_t lds = xw_lds_bytes(h->xwin_max, h->xseg_max, h->xdt == SELL_F64 ? 8 : 4, h->xw_gc);
     e = sell::launch_spmv_xw(h->combo, h->C, h->g.V, h->unroll / h->g.V, a, w, lds, static_cast<hipStream_t>(stream));
   } else {
     e = sell::launch_spmv(h->combo, h->C, h->unroll / h->g.V, h->g.V, skip_zero, a, static_cast<hipStream_t>(stream));
@@ -737,7 +764,7 @@ extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
   r.xwindow = h->lcol ? 1 : 0;
   r.xwindow_max = h->xwin_max;
   r.xsegments = h->nxseg;
-  r.xwindow_group_chunks = sell::kXwChunks;
+  r.xwindow_group_chunks = h->lcol ? h->xw_gc : 0;
   *info = r;
   return SELL_OK;
 }
@@ -762,7 +789,7 @@ extern "C" sell_status sell_export_xwindow(sell_handle h, int64_t *segoff, int32
   if (!h) return fail(SELL_ERR_INVALID_ARG, "sell_export_xwindow: null handle");
   if (!h->lcol) return fail(SELL_ERR_UNSUPPORTED, "sell_export_xwindow: the handle has no x window");
   SELL_HIP(hipDeviceSynchronize());
-  const int64_t ngroups = (h->nchunks + sell::kXwChunks - 1) / sell::kXwChunks;
+  const int64_t ngroups = (h->nchunks + h->xw_gc - 1) / h->xw_gc;
   if (segoff)
     SELL_HIP(hipMemcpy(segoff, h->xsegoff, sizeof(int64_t) * (size_t)(ngroups + 1), hipMemcpyDeviceToHost));
   if (seg && h->nxseg > 0)

@@ -133,15 +133,18 @@ struct BatchArgs {
   int32_t seg_cols;
 };
 
-// x window of a product workgroup (LDS staging): groups of kXwChunks
-// consecutive chunks, at most kXwMaxSlots slots each.
+// x window of a product workgroup (LDS staging): groups of G consecutive
+// chunks (G = kXwChunksWide when the windows of that many fit, else
+// kXwChunks), at most kXwMaxSlots slots each.
 constexpr int kXwChunks = 4;
+constexpr int kXwChunksWide = 8;
 constexpr int kXwMaxSlots = 8192;
 struct XwArgs {
   const uint16_t *lcol;   // window position of every slot
   const int64_t *segoff;  // ngroups + 1 segment offsets
   const int32_t *seg;     // per segment: start column, window position, length
   int32_t wcap;           // LDS elements reserved for the window (the largest one)
+  int32_t gc;             // chunks per group (one wave each): kXwChunks or kXwChunksWide
 };
 // Most segments a group's window may have (its table is staged in LDS too).
 constexpr int kXwMaxSeg = 1024;
@@ -190,14 +193,14 @@ hipError_t build_fill(const int64_t *rpt, const int32_t *col, const double *val,
                       int64_t padded, const int32_t *cmap, int32_t *scol, void *sval, int val_dtype,
                       hipStream_t s);
 hipError_t build_invert(const int32_t *perm, int64_t n, int32_t *iperm, hipStream_t s);
-// x windows: segment count per group (nseg: ngroups + 1 int64, the last set
-// to 0), the largest window (*maxwin, zeroed by the caller), flag bit 1 when
-// a group holds more than kXwMaxSlots slots; then the segments and the
-// window position of every slot.
-hipError_t build_xw_count(const int32_t *col, const int64_t *cs, int64_t nchunks, int64_t *nseg, uint32_t *flags,
-                          int32_t *maxwin, int32_t *maxseg, hipStream_t s);
-hipError_t build_xw_fill(const int32_t *col, const int64_t *cs, int64_t nchunks, const int64_t *segoff, int32_t *seg,
-                         uint16_t *lcol, hipStream_t s);
+// x windows of groups of gc consecutive chunks: segment count per group
+// (nseg: ngroups + 1 int64, the last set to 0), the largest window (*maxwin,
+// zeroed by the caller), flag bit 1 when a group holds more than kXwMaxSlots
+// slots; then the segments and the window position of every slot.
+hipError_t build_xw_count(const int32_t *col, const int64_t *cs, int64_t nchunks, int gc, int64_t *nseg,
+                          uint32_t *flags, int32_t *maxwin, int32_t *maxseg, hipStream_t s);
+hipError_t build_xw_fill(const int32_t *col, const int64_t *cs, int64_t nchunks, int gc, const int64_t *segoff,
+                         int32_t *seg, uint16_t *lcol, hipStream_t s);
 // out[p] = in[perm[p]] (scatter = false) or out[perm[p]] = in[p] (scatter = true).
 hipError_t permute_vector(const void *in, void *out, const int32_t *perm, int64_t n, int elem_bytes, bool scatter,
                           hipStream_t s);
@@ -259,6 +262,7 @@ struct sell_matrix {
   int64_t nxseg = 0;
   int32_t xwin_max = 0;         // largest window, in x elements
   int32_t xseg_max = 0;         // most segments of one window
+  int32_t xw_gc = 0;            // chunks per window group
 
   std::vector<int32_t> h_cl;    // host copy of the chunk widths (batch planning)
 

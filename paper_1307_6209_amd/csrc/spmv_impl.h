@@ -298,8 +298,7 @@ __device__ __forceinline__ void ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t slot, 
   }
 }
 
-// Product with the x window in LDS. Workgroup g (kXwChunks waves, one chunk
-// each) first issues its first U wave steps of val and of the 16-bit window
+// Product with the x window in LDS. Workgroup g (GC waves, one chunk each) first issues its first U wave steps of val and of the 16-bit window
 // positions, then stages its window -- every element with one load, its
 // segment found by binary search -- and after the barrier runs the steps of
 // spmv_unit (same lanes, same order of the multiply-adds, same cross-lane
@@ -307,8 +306,8 @@ __device__ __forceinline__ void ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t slot, 
 // from LDS.
 constexpr int64_t kXcdTile = 16;  // groups of chunks per XCD tile
 
-template <int COMBO, int C, int VV, int U>
-__global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs xa) {
+template <int COMBO, int C, int VV, int U, int GC>
+__global__ void __launch_bounds__(64 * GC) k_spmv_xw(SpmvArgs a, XwArgs xa) {
   using V = typename Types<COMBO>::V;
   using X = typename Types<COMBO>::X;
   using A = typename Types<COMBO>::A;
@@ -331,7 +330,7 @@ __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs x
   }
   const int lane = threadIdx.x & 63;
   // the wave's chunk, marked uniform so that its descriptors are scalar
-  const int64_t chunk = g * kXwChunks + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t chunk = g * GC + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool live = chunk < a.nwork;
   const int64_t base = live ? a.cs[chunk] : 0;
   const int cl = live ? a.cl[chunk] : 0;
@@ -369,16 +368,16 @@ __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs x
   {
     const X *x = static_cast<const X *>(a.x);
     segt[threadIdx.x] = seg0;
-    for (int k = threadIdx.x + 64 * kXwChunks; k < ns; k += 64 * kXwChunks)
+    for (int k = threadIdx.x + 64 * GC; k < ns; k += 64 * GC)
       segt[k] = make_int2(xa.seg[3 * (s0 + k)], xa.seg[3 * (s0 + k) + 1]);
     const int nwin = ns > 0 ? xa.seg[3 * (s0 + ns - 1) + 1] + xa.seg[3 * (s0 + ns - 1) + 2] : 0;
     __syncthreads();
     constexpr int K = 8;
-    for (int b = 0; b < nwin; b += 64 * kXwChunks * K) {
+    for (int b = 0; b < nwin; b += 64 * GC * K) {
       X tmp[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int i = b + k * 64 * kXwChunks + (int)threadIdx.x;
+        const int i = b + k * 64 * GC + (int)threadIdx.x;
         tmp[k] = (X)0;
         if (i < nwin) {
           int lo = 0, hi = ns - 1;  // last segment with position <= i
@@ -392,7 +391,7 @@ __global__ void __launch_bounds__(64 * kXwChunks) k_spmv_xw(SpmvArgs a, XwArgs x
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int i = b + k * 64 * kXwChunks + (int)threadIdx.x;
+        const int i = b + k * 64 * GC + (int)threadIdx.x;
         if (i < nwin) xw[i] = tmp[k];
       }
     }
@@ -948,14 +947,14 @@ hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a
   return skip_zero ? launch_spmv_zs<COMBO, true>(C, U, VV, a, s) : launch_spmv_zs<COMBO, false>(C, U, VV, a, s);
 }
 
-// C in {8, 16, 32, 64}; U * V slots in flight per lane: 4 or 8.
-template <int COMBO>
-hipError_t launch_spmv_xw_t(int C, int VV, int U, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
-  if (a.nwork <= 0) return hipSuccess;
-  const unsigned nb = (unsigned)((a.nwork + kXwChunks - 1) / kXwChunks);
+// C in {8, 16, 32, 64}; U * V slots in flight per lane: 4 or 8; w.gc chunks
+// per workgroup: kXwChunks or kXwChunksWide.
+template <int COMBO, int GC>
+hipError_t launch_spmv_xw_g(int C, int VV, int U, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.nwork + GC - 1) / GC);
 #define SELL_L(CC, VVV, UU)                                                                                    \
   if (C == CC && VV == VVV && U == UU) {                                                                       \
-    hipLaunchKernelGGL((k_spmv_xw<COMBO, CC, VVV, UU>), dim3(nb), dim3(64 * kXwChunks), lds, s, a, w);        \
+    hipLaunchKernelGGL((k_spmv_xw<COMBO, CC, VVV, UU, GC>), dim3(nb), dim3(64 * GC), lds, s, a, w);           \
     return hipGetLastError();                                                                                  \
   }
   SELL_L(8, 1, 4) SELL_L(16, 1, 4) SELL_L(32, 1, 4) SELL_L(64, 1, 4)
@@ -964,6 +963,14 @@ hipError_t launch_spmv_xw_t(int C, int VV, int U, const SpmvArgs &a, const XwArg
   SELL_L(8, 2, 4) SELL_L(16, 2, 4) SELL_L(32, 2, 4) SELL_L(64, 2, 4)
   SELL_L(8, 2, 8) SELL_L(16, 2, 8) SELL_L(32, 2, 8) SELL_L(64, 2, 8)
 #undef SELL_L
+  return hipErrorInvalidValue;
+}
+
+template <int COMBO>
+hipError_t launch_spmv_xw_t(int C, int VV, int U, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
+  if (a.nwork <= 0) return hipSuccess;
+  if (w.gc == kXwChunks) return launch_spmv_xw_g<COMBO, kXwChunks>(C, VV, U, a, w, lds, s);
+  if (w.gc == kXwChunksWide) return launch_spmv_xw_g<COMBO, kXwChunksWide>(C, VV, U, a, w, lds, s);
   return hipErrorInvalidValue;
 }
 

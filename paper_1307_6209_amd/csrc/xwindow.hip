@@ -1,5 +1,5 @@
 // The x window of each product workgroup: the distinct column indices that
-// the slots of its kXwChunks consecutive chunks hold, sorted. The product
+// the slots of its consecutive chunks (a group of gc) hold, sorted. The product
 // kernel stages the window in LDS once per workgroup, and every slot's
 // column index is stored a second time as its 16-bit position in the window,
 // so the x gathers become LDS reads and the streamed index shrinks from 4 to
@@ -61,7 +61,7 @@ __device__ __forceinline__ uint32_t run_ends(const uint32_t *bm, int w, int nw) 
   return x & ~((x >> 1) | next);
 }
 
-// One workgroup per group of kXwChunks chunks.
+// One workgroup per group of gc chunks.
 // PASS 0: segment count per group into nseg[g] (and nseg[ngroups] = 0 for
 //         the scan), the largest window into *maxwin and the most segments
 //         of a group into *maxseg, flag bit 1 when a group holds more than
@@ -77,7 +77,8 @@ __device__ __forceinline__ uint32_t run_ends(const uint32_t *bm, int w, int nw) 
 // Both ways give the same window, runs and positions.
 template <int PASS>
 __global__ void __launch_bounds__(kXwBlock) k_xw_groups(const int32_t *__restrict__ col, const int64_t *__restrict__ cs,
-                                                        int64_t nchunks, int64_t ngroups, int64_t *__restrict__ nseg,
+                                                        int64_t nchunks, int gc, int64_t ngroups,
+                                                        int64_t *__restrict__ nseg,
                                                         uint32_t *flags, int32_t *maxwin, int32_t *maxseg,
                                                         const int64_t *__restrict__ segoff, int32_t *__restrict__ seg,
                                                         uint16_t *__restrict__ lcol) {
@@ -89,8 +90,8 @@ __global__ void __launch_bounds__(kXwBlock) k_xw_groups(const int32_t *__restric
   const int64_t g = blockIdx.x;
   const int tid = threadIdx.x;
   if (PASS == 0 && g == 0 && tid == 0) nseg[ngroups] = 0;
-  const int64_t c0 = g * kXwChunks;
-  const int64_t c1 = c0 + kXwChunks < nchunks ? c0 + kXwChunks : nchunks;
+  const int64_t c0 = g * gc;
+  const int64_t c1 = c0 + gc < nchunks ? c0 + gc : nchunks;
   const int64_t sb = cs[c0], se = cs[c1];
   if (se - sb > kXwMaxSlots) {  // uniform over the block
     if (PASS == 0 && tid == 0) {
@@ -280,20 +281,22 @@ __global__ void __launch_bounds__(kXwBlock) k_xw_groups(const int32_t *__restric
 
 }  // namespace
 
-hipError_t build_xw_count(const int32_t *col, const int64_t *cs, int64_t nchunks, int64_t *nseg, uint32_t *flags,
-                          int32_t *maxwin, int32_t *maxseg, hipStream_t s) {
-  const int64_t ngroups = (nchunks + kXwChunks - 1) / kXwChunks;
+hipError_t build_xw_count(const int32_t *col, const int64_t *cs, int64_t nchunks, int gc, int64_t *nseg,
+                          uint32_t *flags, int32_t *maxwin, int32_t *maxseg, hipStream_t s) {
+  if (gc <= 0) return hipErrorInvalidValue;
+  const int64_t ngroups = (nchunks + gc - 1) / gc;
   if (ngroups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xw_groups<0>, dim3((unsigned)ngroups), dim3(kXwBlock), 0, s, col, cs, nchunks, ngroups, nseg,
-                     flags, maxwin, maxseg, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_xw_groups<0>, dim3((unsigned)ngroups), dim3(kXwBlock), 0, s, col, cs, nchunks, gc, ngroups,
+                     nseg, flags, maxwin, maxseg, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
-hipError_t build_xw_fill(const int32_t *col, const int64_t *cs, int64_t nchunks, const int64_t *segoff, int32_t *seg,
-                         uint16_t *lcol, hipStream_t s) {
-  const int64_t ngroups = (nchunks + kXwChunks - 1) / kXwChunks;
+hipError_t build_xw_fill(const int32_t *col, const int64_t *cs, int64_t nchunks, int gc, const int64_t *segoff,
+                         int32_t *seg, uint16_t *lcol, hipStream_t s) {
+  if (gc <= 0) return hipErrorInvalidValue;
+  const int64_t ngroups = (nchunks + gc - 1) / gc;
   if (ngroups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xw_groups<1>, dim3((unsigned)ngroups), dim3(kXwBlock), 0, s, col, cs, nchunks, ngroups,
+  hipLaunchKernelGGL(k_xw_groups<1>, dim3((unsigned)ngroups), dim3(kXwBlock), 0, s, col, cs, nchunks, gc, ngroups,
                      nullptr, nullptr, nullptr, nullptr, segoff, seg, lcol);
   return hipGetLastError();
 }

@@ -85,14 +85,14 @@ def algorithmic_bytes(nrows: int, ncols: int, padded: int, nchunks: int, k: int 
 
 
 def sizes_for(val_dtype: str, acc_dtype: str, sigma_gt_1: bool, xwindow: bool = False,
-              segments_per_chunk: float = 0.0) -> Sizes:
+              segments_per_chunk: float = 0.0, group_chunks: int = 4) -> Sizes:
     """Element sizes of a product. With the x window staged in LDS the
     streamed index is the 2-byte window position, and each chunk also moves
-    its share of the window tables: 2 bytes of group offsets (8 bytes per
-    group of 4 chunks) and 12 bytes per segment."""
+    its share of the window tables: 8 bytes of group offsets per group of
+    group_chunks chunks and 12 bytes per segment."""
     sv = {"f64": 8, "f32": 4, "bf16": 2}[val_dtype]
     sx = 8 if val_dtype == "f64" else 4
     sy = 8 if acc_dtype == "f64" else 4
     if xwindow:
-        return Sizes(sv=sv, si=2, sx=sx, sy=sy, sp=4 if sigma_gt_1 else 0, meta=12 + 2 + 12 * segments_per_chunk)
+        return Sizes(sv=sv, si=2, sx=sx, sy=sy, sp=4 if sigma_gt_1 else 0, meta=12 + 8 / group_chunks + 12 * segments_per_chunk)
     return Sizes(sv=sv, si=4, sx=sx, sy=sy, sp=4 if sigma_gt_1 else 0)

@@ -42,7 +42,7 @@ class SellAllocator(ctypes.Structure):
 class SellBuildOpts(ctypes.Structure):
     _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("vec", c_i32),
                 ("seg_cols", c_i32), ("ktile", c_i32), ("kmax", c_i32), ("permute_columns", c_i32),
-                ("xwindow", c_i32), ("alloc", ctypes.POINTER(SellAllocator))]
+                ("xwindow", c_i32), ("alloc", ctypes.POINTER(SellAllocator)), ("xwindow_chunks", c_i32)]
 
 
 class SellInfo(ctypes.Structure):
@@ -252,9 +252,10 @@ class SellMatrix:
 def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
                unroll: int = 0, vec: int = 0, seg_cols: int = 0, ktile: int = 0, kmax: int = 0,
                permute_columns: bool = False, xwindow: int = 0, allocator: TorchAllocator | None = None,
-               stream=None) -> SellMatrix:
+               stream=None, xwindow_chunks: int = 0) -> SellMatrix:
     """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64).
     xwindow: 0 stage x windows in LDS when they fit, -1 never, 1 required.
+    xwindow_chunks: chunks per window group, 0 auto (8 at C = 32 when they fit), 4 or 8.
     allocator: a TorchAllocator to take the handle's device memory from
     torch's caching allocator (default: the library's hipMalloc)."""
     import torch
@@ -266,7 +267,7 @@ def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
     o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax,
                       1 if permute_columns else 0, xwindow,
-                      ctypes.pointer(allocator.struct) if allocator else None)
+                      ctypes.pointer(allocator.struct) if allocator else None, xwindow_chunks)
     h = c_p()
     _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
     return SellMatrix(h, allocator)
@@ -328,6 +329,8 @@ def sell_export_xwindow(h: SellMatrix) -> dict:
     seg (xsegments x 3: first column, window position, length) and lcol
     (window position of every slot)."""
     inf = h.info
+    if not inf["xwindow"]:  # the library reports the error
+        _check(lib().sell_export_xwindow(h.handle, None, None, None), "sell_export_xwindow")
     G = inf["xwindow_group_chunks"]
     ngroups = (inf["nchunks"] + G - 1) // G
     out = {"segoff": np.empty(ngroups + 1, np.int64), "seg": np.empty((inf["xsegments"], 3), np.int32),

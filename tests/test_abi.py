@@ -83,6 +83,10 @@ def test_host_side_argument_errors(L):
         badx = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, xwindow=xw)
         assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badx), None,
                             ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    for g in (-1, 2, 16):
+        badg = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, xwindow_chunks=g)
+        assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badg), None,
+                            ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmv(None, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmmv(None, None, None, 4, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_batch_create(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG

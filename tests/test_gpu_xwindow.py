@@ -33,6 +33,34 @@ def banded(n, seed, half=40, max_len=30):
     return synth.CRS(n, n, rpt, cc, val)
 
 
+def fits_group(A, C, sigma, gc, x_bytes=8):
+    """Whether the required window of groups of gc chunks can be built: every
+    group holds at most 8,192 slots and 1,024 runs of consecutive columns,
+    and its window at most 16 KiB per chunk of the group."""
+    lay = oracle.sell_build(A, C, sigma)
+    cs = lay["cs"]
+    nc = cs.size - 1
+    starts = np.arange(0, nc, gc)
+    if int(np.max(cs[np.minimum(starts + gc, nc)] - cs[starts])) > 8192:
+        return False
+    segoff, seg, _ = window_tables(lay["col"], cs, gc)
+    runs = np.diff(segoff)
+    win = np.add.reduceat(seg[:, 2], segoff[:-1][runs > 0]) if seg.shape[0] else np.zeros(1, np.int64)
+    return int(runs.max()) <= 1024 and int(win.max()) * x_bytes <= (16 << 10) * gc
+
+
+def build_or_refused(A, C, sigma, gc, **kw):
+    """The window build with groups of gc chunks, or None after checking that
+    it is refused because a group holds too many slots."""
+    from paper_1307_6209_amd import sellcs
+    if fits_group(A, C, sigma, gc):
+        return build(A, C, sigma, xwindow=1, xwindow_chunks=gc, **kw)
+    with pytest.raises(sellcs.SellError) as e:
+        build(A, C, sigma, xwindow=1, xwindow_chunks=gc, **kw)
+    assert e.value.status == sellcs.SELL_ERR_UNSUPPORTED
+    return None
+
+
 MATS = [
     ("stencil27_24", lambda: synth.stencil27(24)),
     ("lap5_96", lambda: synth.lap5(96)),
@@ -40,18 +68,22 @@ MATS = [
 ]
 
 
+@pytest.mark.parametrize("gc", [4, 8])
 @pytest.mark.parametrize("name,make", MATS, ids=[m[0] for m in MATS])
 @pytest.mark.parametrize("C,sigma,vec", [(32, 1, 0), (32, 1, 1), (8, 1, 2), (16, 64, 0), (64, 1, 0), (64, 4096, 1),
                                          (32, 10**9, 2)])
-def test_window_equals_global_index_product(name, make, C, sigma, vec):
+def test_window_equals_global_index_product(name, make, C, sigma, vec, gc):
+    """Groups of 4 and of 8 chunks (one workgroup of 4 or 8 waves)."""
     A = make()
     x = synth.uniform(A.ncols, 31, 1)
-    on = build(A, C, sigma, vec=vec, xwindow=1)
+    on = build_or_refused(A, C, sigma, gc, vec=vec)
+    if on is None:
+        return
     off = build(A, C, sigma, vec=vec, xwindow=-1)
     inf = on.info
-    say("xwindow", name, "C", C, "sigma", sigma, "vec", inf["vec"], "window", inf["xwindow_max"], "segments",
-        inf["xsegments"])
-    assert inf["xwindow"] == 1 and off.info["xwindow"] == 0
+    say("xwindow", name, "C", C, "sigma", sigma, "vec", inf["vec"], "chunks", gc, "window", inf["xwindow_max"],
+        "segments", inf["xsegments"])
+    assert inf["xwindow"] == 1 and off.info["xwindow"] == 0 and inf["xwindow_group_chunks"] == gc
     y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
     assert np.array_equal(y_on.view(np.uint64), y_off.view(np.uint64))
     check_fp64(A, y_on, x)
@@ -146,9 +178,20 @@ def test_window_auto_falls_back_and_required_is_refused():
             build(S, C, 1, xwindow=1, **kw)
         assert build(S, C, 1, **kw).info["xwindow"] == 0  # auto: the plain kernel
     # the default build uses the window on a banded matrix with enough groups
-    # of chunks (two per compute unit), not on a small one
+    # of chunks (two per compute unit), not on a small one; at C = 32 groups
+    # of 8 chunks when there are two of those per compute unit, else of 4
     assert build(S, 32, 1).info["xwindow"] == 0
-    assert build(synth.stencil27(64), 32, 1).info["xwindow"] == 1
+    inf = build(synth.stencil27(64), 32, 1).info  # 8,192 chunks
+    assert inf["xwindow"] == 1 and inf["xwindow_group_chunks"] == 8
+    for C in (16, 64):  # the wide groups only at C = 32
+        inf = build(synth.stencil27(64), C, 1).info
+        assert inf["xwindow"] == 1 and inf["xwindow_group_chunks"] == 4
+    inf = build(synth.stencil27(48), 32, 1).info  # 3,456 chunks: 432 groups of 8, 864 of 4
+    assert inf["xwindow"] == 1 and inf["xwindow_group_chunks"] == 4
+    # an explicit size is built as asked, or refused when required
+    assert build(synth.stencil27(48), 32, 1, xwindow_chunks=8).info["xwindow_group_chunks"] == 8
+    with pytest.raises(sellcs.SellError):
+        build(scattered_runs(n=3000), 32, 1, xwindow=1, xwindow_chunks=8)  # 15,360 slots per group
 
 
 def test_window_ragged_groups_and_empty_rows():
@@ -160,10 +203,11 @@ def test_window_ragged_groups_and_empty_rows():
         if A.nnz == 0:
             continue
         for C in (8, 32, 64):
-            on = build(A, C, 1, xwindow=1)
             off = build(A, C, 1, xwindow=-1)
-            assert on.info["xwindow"] == 1, (n, C)
-            assert np.array_equal(spmv_gpu(on, x).view(np.uint64), spmv_gpu(off, x).view(np.uint64))
+            for gc in (4, 8):
+                on = build(A, C, 1, xwindow=1, xwindow_chunks=gc)
+                assert on.info["xwindow"] == 1, (n, C, gc)
+                assert np.array_equal(spmv_gpu(on, x).view(np.uint64), spmv_gpu(off, x).view(np.uint64))
 
 
 def blocks_with_empty_runs(seed):
@@ -181,15 +225,17 @@ def blocks_with_empty_runs(seed):
     return synth.CRS(A.nrows, A.ncols, rpt, A.col[sel], A.val[sel])
 
 
+@pytest.mark.parametrize("gc", [4, 8])
 @pytest.mark.parametrize("C", [8, 32, 64])
 @pytest.mark.parametrize("unroll", [4, 16])
-def test_window_empty_chunks_and_groups(C, unroll):
+def test_window_empty_chunks_and_groups(C, unroll, gc):
     """Live waves whose chunk holds no column read nothing and store zeros;
     groups without a slot stage an empty window; the rest of the product is
     untouched (bit-exact against the global-index product)."""
     A = blocks_with_empty_runs(41)
     x = synth.uniform(A.ncols, 36, 1)
-    on = build(A, C, 1, vec=2, unroll=unroll, xwindow=1)
+    assert fits_group(A, C, 1, gc)
+    on = build(A, C, 1, vec=2, unroll=unroll, xwindow=1, xwindow_chunks=gc)
     off = build(A, C, 1, vec=2, xwindow=-1)
     assert on.info["xwindow"] == 1
     y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
@@ -201,8 +247,10 @@ def test_window_empty_chunks_and_groups(C, unroll):
 def scattered_runs(n=66_000, run=60, ncols=1_000_000, seed=77):
     """Each row holds `run` consecutive columns at a random offset: a group
     of 4 chunks of 32 rows has a window of ~7,700 columns in 128 runs
-    (61 KB in FP64, above the automatic 16 KiB limit); 516 groups, more than
-    two per compute unit, so the window size alone decides the default."""
+    (61 KB in FP64, above the automatic 16 KiB limit of 4 chunks); 516
+    groups, more than two per compute unit, so the window size alone decides
+    the default. A group of 8 such chunks holds 15,360 slots, more than a
+    group may hold."""
     off = (synth.uniform(n, seed, 1, 0.0, 1.0) * (ncols - run)).astype(np.int64)
     rpt = np.arange(n + 1, dtype=np.int64) * run
     col = (off[:, None] + np.arange(run)[None, :]).reshape(-1).astype(np.int32)
@@ -213,8 +261,9 @@ def scattered_runs(n=66_000, run=60, ncols=1_000_000, seed=77):
 @pytest.mark.parametrize("val_dtype,acc", [("f64", "f64"), ("f32", "f32")])
 def test_window_largest_required(val_dtype, acc):
     """Windows beyond the automatic limit: the default build falls back to
-    the global-index product; xwindow = 1 builds them (up to 64 KiB of LDS)
-    and the product still equals the global-index one bit for bit."""
+    the global-index product; xwindow = 1 builds them (groups of 4 chunks, up
+    to 64 KiB of LDS) and the product still equals the global-index one bit
+    for bit."""
     A = scattered_runs()
     x = synth.uniform(A.ncols, 37, 1)
     if val_dtype != "f64":
@@ -224,7 +273,7 @@ def test_window_largest_required(val_dtype, acc):
     on = build(A, 32, 1, val_dtype=val_dtype, acc_dtype=acc, vec=2, xwindow=1)
     inf = on.info
     say("largest window", val_dtype, inf["xwindow_max"], "segments", inf["xsegments"])
-    assert inf["xwindow"] == 1 and inf["xwindow_max"] > 7000
+    assert inf["xwindow"] == 1 and inf["xwindow_max"] > 7000 and inf["xwindow_group_chunks"] == 4
     off = build(A, 32, 1, val_dtype=val_dtype, acc_dtype=acc, vec=2, xwindow=-1)
     y_on, y_off = spmv_gpu(on, x), spmv_gpu(off, x)
     assert np.array_equal(y_on, y_off)
@@ -266,16 +315,19 @@ TABLE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("gc", [4, 8])
 @pytest.mark.parametrize("name,make,C,sigma,vec", TABLE_CASES, ids=[c[0] for c in TABLE_CASES])
-def test_window_tables_match_definition(name, make, C, sigma, vec):
+def test_window_tables_match_definition(name, make, C, sigma, vec, gc):
     """The window tables the builder stores (run offsets per group, the runs,
     the 16-bit position of every slot) against their plain definition --
     sorted distinct columns of each group of chunks, position = rank -- taken
-    from the oracle's layout, for every group."""
+    from the oracle's layout, for every group; groups of 4 and of 8 chunks."""
     from paper_1307_6209_amd import sellcs
     A = make()
-    h = build(A, C, sigma, vec=vec, xwindow=1)
-    assert h.info["xwindow"] == 1
+    h = build_or_refused(A, C, sigma, gc, vec=vec)
+    if h is None:
+        return
+    assert h.info["xwindow"] == 1 and h.info["xwindow_group_chunks"] == gc
     got = sellcs.sell_export_xwindow(h)
     lay = oracle.sell_build(A, C, sigma)
     segoff, seg, lcol = window_tables(lay["col"], lay["cs"], got["group_chunks"])

@@ -52,10 +52,12 @@ def test_algorithmic_bytes_27pt():
 
 def test_window_sizes():
     """With the x window the streamed index is 2 bytes and each chunk carries
-    its share of the window tables (8 bytes per group of 4 chunks, 12 per
-    segment)."""
+    its share of the window tables (8 bytes per group of 4 or 8 chunks, 12
+    per segment)."""
     s = model.sizes_for("f64", "f64", False, xwindow=True, segments_per_chunk=2.5)
     assert (s.sv, s.si, s.sx, s.sy, s.sp) == (8, 2, 8, 8, 0)
     assert s.meta == 12 + 2 + 30
     b = model.algorithmic_bytes(100, 100, 1000, 10, 1, s)
     assert b == 10 * 1000 + 8 * 100 + 8 * 100 + 44 * 10
+    s8 = model.sizes_for("f64", "f64", False, xwindow=True, segments_per_chunk=2.5, group_chunks=8)
+    assert s8.meta == 12 + 1 + 30
