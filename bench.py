@@ -65,13 +65,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(src_hash: str):
+def stored_traffic(src_hash: str, split: bool = False):
+    """The stored HBM bytes per launch of the headline kernel (with split,
+    the (fetched, written) pair), when taken on the current kernel sources."""
     p = TRAFFIC_FILE
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_hash") != src_hash:
         return None
+    if split:
+        return d.get("fetch_bytes_per_launch"), d.get("write_bytes_per_launch")
     return d.get("hbm_bytes_per_launch")
 
 
@@ -114,7 +118,8 @@ def store_traffic(fetch_db: str, write_db: str) -> dict:
            "copy_calibration": {"bytes_read_and_written": copy_bytes, "fetch_kib": round(mean(fetch[copy]), 1),
                                 "write_kib": round(mean(write[copy]), 1), "fetch_factor": round(ff, 4),
                                 "write_factor": round(wf, 4)},
-           "hbm_bytes_per_launch": int(round(fb + wb)), "kernel_source_hash": kernel_source_hash()}
+           "hbm_bytes_per_launch": int(round(fb + wb)), "fetch_bytes_per_launch": int(round(fb)),
+           "write_bytes_per_launch": int(round(wb)), "kernel_source_hash": kernel_source_hash()}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -260,6 +265,21 @@ def cold_time(fn, flush, reps: int = 21) -> float:
     return ts[len(ts) // 2] * 1e-3
 
 
+def read_write_bound(read_bytes, write_bytes, probes, sec, traffic=None) -> dict:
+    """Time to read read_bytes at the read probe's rate and then write
+    write_bytes at the write probe's rate, and the measured time's fraction
+    of it; with stored counters (fetched, written) also for those bytes."""
+    t = read_bytes / (probes["read_gbs"] * 1e9) + write_bytes / (probes["write_gbs"] * 1e9)
+    out = {"read_bytes": int(read_bytes), "write_bytes": int(write_bytes), "us": round(t * 1e6, 2),
+           "frac": round(t / sec, 4),
+           "basis": "bytes the format moves: reads at read_gbs, the result's writes at write_gbs, in turn"}
+    if traffic and traffic[0] and traffic[1]:
+        tc = traffic[0] / (probes["read_gbs"] * 1e9) + traffic[1] / (probes["write_gbs"] * 1e9)
+        out["counted_us"] = round(tc * 1e6, 2)
+        out["counted_frac"] = round(tc / sec, 4)
+    return out
+
+
 def run_forms(args, probes, checks, checks_x) -> dict:
     import torch
     import numpy as np
@@ -284,19 +304,41 @@ def run_forms(args, probes, checks, checks_x) -> dict:
     progress("block form")
     A = synth.workload("powerlaw_1m")
     r, c, v = to_dev(A)
-    spmmv = {}
+    spmmv, ceiling = {}, {}
+    rows_pow2 = 1 << (A.nrows - 1).bit_length()
     for C, sg in ((32, 1024), (32, A.nrows)):
         h = sellcs.sell_build(r, c, v, A.ncols, C, sg, kmax=64)
+        inf = h.info
         for k in (1, 4, 8, 16, 32, 64):
             X = torch.from_numpy(synth.block_vector(A.ncols, k)).cuda()
             Y = torch.empty(A.nrows, k, dtype=torch.float64, device="cuda")
             t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
             spmmv["C%d_sigma%d_k%d" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
+            if sg == A.nrows and k in (16, 32, 64):
+                # one random row of X (8k bytes) per nonzero at the random-row
+                # probe's rate over an array of X's size, the matrix (12 B
+                # per slot, cl and cs, the permutation) at the read rate, and
+                # Y at the write rate, in turn
+                rows_gbs = sellcs.sell_probe_bandwidth({16: 3, 32: 4, 64: 5}[k], rows_pow2 * 8 * k, 5)
+                mat = 12 * inf["padded"] + 12 * inf["nchunks"] + 4 * A.nrows
+                tc = (8.0 * k * A.nnz / (rows_gbs * 1e9) + mat / (probes["read_gbs"] * 1e9)
+                      + 8.0 * k * A.nrows / (probes["write_gbs"] * 1e9))
+                # the same rows read and written at the rate of the probe
+                # that mixes them (four random rows read per row written)
+                mixed_gbs = sellcs.sell_probe_bandwidth({16: 7, 32: 8, 64: 9}[k], rows_pow2 * 8 * k, 5)
+                tm = 8.0 * k * (A.nnz + A.nrows) / (mixed_gbs * 1e9) + mat / (probes["read_gbs"] * 1e9)
+                ceiling["k%d" % k] = {"rows_probe_gbs": round(rows_gbs, 1), "ceiling_us": round(tc * 1e6, 2),
+                                      "us": round(t * 1e6, 2), "frac": round(tc / t, 4),
+                                      "mixed_probe_gbs": round(mixed_gbs, 1),
+                                      "mixed_ceiling_us": round(tm * 1e6, 2), "frac_mixed": round(tm / t, 4),
+                                      "x_rows_per_s_g": round(A.nnz / t * 1e-9, 2),
+                                      "probe_rows_per_s_g": round(rows_gbs / (8.0 * k), 2)}
             if sg == A.nrows and k in (1, 8, 32):
                 t = cold_time(lambda: sellcs.sell_spmmv(h, X, Y), flush)
                 spmmv["C%d_sigma%d_k%d_cold" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
         h.close()
     out["spmmv_powerlaw_1m_gfs"] = spmmv
+    out["spmmv_powerlaw_1m_sigma_n_ceiling"] = ceiling
     # the block form autotuned over C, sigma and the pass width (0: the
     # automatic choice, which includes the one-pass kernels)
     tuned = {}
@@ -624,7 +666,12 @@ def main():
               # random 8-byte gathers (8 B counted per gather) over arrays the
               # size of the power-law x (16 MiB) and far beyond the MALL
               "gather_16mib_gbs": round(sellcs.sell_probe_bandwidth(2, 16 << 20, 5), 1),
-              "gather_2gib_gbs": round(sellcs.sell_probe_bandwidth(2, 2 << 30, 5), 1)}
+              "gather_2gib_gbs": round(sellcs.sell_probe_bandwidth(2, 2 << 30, 5), 1),
+              "write_gbs": round(sellcs.sell_probe_bandwidth(6, 4 << 30, 10), 1)}
+    # reads and writes taking turns on the memory: a copy of B bytes would
+    # take B / read + B / write; the copy probe checks that model
+    probes["copy_predicted_by_read_and_write_gbs"] = round(
+        2.0 / (1.0 / probes["read_gbs"] + 1.0 / probes["write_gbs"]), 1)
 
     sec = time_calls(lambda: sellcs.sell_spmv(h, x, y), args.steps, args.warmup, repeats=1)
     gfs = 2.0 * A.nnz / sec * 1e-9
@@ -681,6 +728,8 @@ def main():
                                        "null: no counter measurement for the current kernel sources (hash %s)"
                                        % src_hash},
         "model": model_report(model, probes["read_gbs"], gfs, achieved_moved, inf, A, sizes, traffic),
+        "read_write_bound": read_write_bound(moved - 8 * A.nrows, 8 * A.nrows, probes, sec,
+                                             stored_traffic(src_hash, split=True) if traffic else None),
         "build_ms": round(build_s * 1e3, 2),
         "probes": probes,
         "kernel_source_hash": src_hash,

@@ -419,10 +419,16 @@ sell_status sell_batch_autotune(const sell_crs *As, int32_t count,
  * 256 or 512 bytes (k = 16, 32, 64) at hashed row positions of an array of
  * the largest power-of-two row count that fits in bytes, 16 bytes per lane;
  * *gbs is then row bytes x rows / time (rows per second = *gbs / row bytes
- * x 1e9).
+ * x 1e9). kind 6 writes bytes with 16-byte non-temporal stores (the store
+ * kind of the products' results): the write-only rate. kinds 7, 8, 9 mix
+ * both as the block form does: P rows of 128, 256 or 512 bytes are written
+ * in order (non-temporal), each the sum of four rows read at hashed row
+ * positions of an input of P rows (P the largest power of two with
+ * P x row bytes <= bytes; a second buffer of bytes holds the output); *gbs
+ * is then 5 x P x row bytes / time.
  * Runs reps timed passes after one warm-up on stream; *gbs receives the mean
  * bandwidth in GB/s (1e9 bytes). Allocates and frees its own buffers.
- * Errors: SELL_ERR_INVALID_ARG for kind outside 0..5, reps < 1 or bytes
+ * Errors: SELL_ERR_INVALID_ARG for kind outside 0..9, reps < 1 or bytes
  * below 1 MiB; SELL_ERR_OOM when the buffers cannot be allocated.
  */
 sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps,

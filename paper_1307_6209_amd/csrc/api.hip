@@ -1376,24 +1376,30 @@ extern "C" sell_status sell_batch_autotune(const sell_crs *As, int32_t count, co
 }
 
 extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps, void *stream, double *gbs) {
-  if (!gbs || reps < 1 || kind < 0 || kind > 5 || bytes < (1u << 20))
+  if (!gbs || reps < 1 || kind < 0 || kind > 9 || bytes < (1u << 20))
     return fail(SELL_ERR_INVALID_ARG, "sell_probe_bandwidth: bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   bytes = bytes / 64 * 64;
   Temp tmp(Mem{});
   const size_t abytes = kind == 1 ? bytes / 2 : bytes;
+  // second buffer: the copy's target, or the output rows of kinds 7-9
+  const size_t bbytes = kind == 1 ? bytes / 2 : kind >= 7 ? bytes : 0;
   void *a = tmp.get(abytes);
-  void *b = kind == 1 ? tmp.get(bytes / 2) : nullptr;
+  void *b = bbytes ? tmp.get(bbytes) : nullptr;
   double *sink = static_cast<double *>(tmp.get(sizeof(double) * 256 * 16));
-  if (!a || !sink || (kind == 1 && !b)) return fail(SELL_ERR_OOM, "sell_probe_bandwidth: buffers");
+  if (!a || !sink || (bbytes && !b)) return fail(SELL_ERR_OOM, "sell_probe_bandwidth: buffers");
   SELL_HIP(hipMemsetAsync(a, 0, abytes, s));
   int64_t moved = (int64_t)bytes;  // bytes counted per pass
   auto run = [&]() {
     if (kind == 0) return sell::probe_read(a, bytes, sink, s);
     if (kind == 1) return sell::probe_copy(a, b, bytes / 2, s);
+    if (kind == 6) return sell::probe_write(a, bytes, s);
     hipError_t e = hipSuccess;
     if (kind == 2) {
       moved = sell::probe_gather(a, bytes, sink, s, &e) * (int64_t)sizeof(double);
+    } else if (kind >= 7) {
+      const int row_bytes = 128 << (kind - 7);  // kinds 7, 8, 9: rows of 128, 256, 512 bytes
+      moved = sell::probe_rows_write(a, b, bytes, row_bytes, s, &e) * (int64_t)row_bytes;
     } else {
       const int row_bytes = 128 << (kind - 3);  // kinds 3, 4, 5: rows of 128, 256, 512 bytes
       moved = sell::probe_rows(a, bytes, row_bytes, sink, s, &e) * (int64_t)row_bytes;

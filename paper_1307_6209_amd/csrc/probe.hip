@@ -6,7 +6,9 @@
 // products whose right-hand-side accesses have no locality; and a random-row
 // rate (whole rows of 128, 256 or 512 bytes at hashed row positions), the
 // same ceiling for the block form, whose k right-hand sides make each
-// access one row of 8k bytes.
+// access one row of 8k bytes; a write-only stream, the rate of the
+// result's stores; and random rows read with rows written in order, four
+// to one, the block form's mix of both.
 #include "sell_internal.h"
 
 namespace sell {
@@ -47,6 +49,26 @@ __global__ void __launch_bounds__(kBlock) k_read(const d2 *__restrict__ a, int64
   // zeroed input)
   double s = s0 + s1;
   if (threadIdx.x == 0 || s != s) sink[blockIdx.x] = s;
+}
+
+// Write-only stream: each wave fills one contiguous slab of the array with
+// eight 16-byte non-temporal stores per lane in flight (the store kind of
+// the products' y and Y).
+__global__ void __launch_bounds__(kBlock) k_write(d2 *__restrict__ a, int64_t n2, int64_t per_wave, double v) {
+  constexpr int U = 8;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t b0 = wave * per_wave;
+  const int64_t b1 = b0 + per_wave < n2 ? b0 + per_wave : n2;
+  d2 w;
+  w.x = v;
+  w.y = v;
+  int64_t i = b0 + lane;
+  for (; i + (U - 1) * 64 < b1; i += U * 64) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(w, a + i + u * 64);
+  }
+  for (; i < b1; i += 64) __builtin_nontemporal_store(w, a + i);
 }
 
 __global__ void __launch_bounds__(kBlock) k_copy(const d2 *__restrict__ a, d2 *__restrict__ b, int64_t n4) {
@@ -108,6 +130,42 @@ __global__ void __launch_bounds__(kBlock) k_rows(const d2 *__restrict__ a, uint3
   if (threadIdx.x == 0 || s != s) sink[blockIdx.x] = s;
 }
 
+// Random rows in, rows out: output row o (rows of 16*LPR bytes, in order)
+// is the sum of four input rows at hashed positions -- the block form's
+// access pattern (a few random rows of X read per row of Y written) without
+// the matrix. Each lane keeps eight row reads in flight (two output rows of
+// its group); consecutive waves write consecutive output rows.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_rows_write(const d2 *__restrict__ a, uint32_t row_mask,
+                                                       d2 *__restrict__ out, int64_t ngroups) {
+  constexpr int RPA = 64 / LPR;  // output rows per access of a wave
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPR, q = lane % LPR;
+  for (int64_t gi = wave; gi < ngroups; gi += 2 * nw) {
+    d2 v[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t gg = gi + h * nw;
+      const uint32_t o = (uint32_t)(gg * RPA + g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t r = lowbias32(o * 4u + (uint32_t)j) & row_mask;
+        v[h][j] = (d2){0.0, 0.0};
+        if (gg < ngroups) v[h][j] = a[(size_t)r * LPR + q];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t gg = gi + h * nw;
+      if (gg < ngroups)
+        __builtin_nontemporal_store(v[h][0] + v[h][1] + v[h][2] + v[h][3],
+                                    out + (size_t)(gg * RPA + g) * LPR + q);
+    }
+  }
+}
+
 }  // namespace
 
 constexpr int kProbeBlocks = 256 * 16;
@@ -149,6 +207,35 @@ int64_t probe_rows(const void *a, size_t bytes, int row_bytes, double *sink, hip
   }
   *err = hipGetLastError();
   return (int64_t)kBlocks * (kBlock / 64) * kPerLane * (64 / lpr);
+}
+
+hipError_t probe_write(void *a, size_t bytes, hipStream_t s) {
+  const int64_t n2 = (int64_t)(bytes / sizeof(d2));
+  const int64_t waves = (int64_t)kProbeBlocks * (kBlock / 64) / 2;  // 8192 slabs
+  const int64_t per_wave = (n2 + waves - 1) / waves;
+  hipLaunchKernelGGL(k_write, dim3((unsigned)(waves * 64 / kBlock)), dim3(kBlock), 0, s, static_cast<d2 *>(a), n2,
+                     per_wave, 0.0);
+  return hipGetLastError();
+}
+
+int64_t probe_rows_write(const void *a, void *out, size_t bytes, int row_bytes, hipStream_t s, hipError_t *err) {
+  const int lpr = row_bytes / (int)sizeof(d2);
+  uint32_t mask = 1;
+  while ((uint64_t)(mask + 1) * 2 * (uint64_t)row_bytes <= bytes && mask < 0x7fffffffu) mask = mask * 2 + 1;
+  const int64_t rows = (int64_t)mask + 1;  // output rows, as many as input rows
+  const int64_t ngroups = rows / (64 / lpr);
+  const dim3 grid(2048), block(kBlock);
+  const d2 *p = static_cast<const d2 *>(a);
+  d2 *o = static_cast<d2 *>(out);
+  if (lpr == 8) hipLaunchKernelGGL(k_rows_write<8>, grid, block, 0, s, p, mask, o, ngroups);
+  else if (lpr == 16) hipLaunchKernelGGL(k_rows_write<16>, grid, block, 0, s, p, mask, o, ngroups);
+  else if (lpr == 32) hipLaunchKernelGGL(k_rows_write<32>, grid, block, 0, s, p, mask, o, ngroups);
+  else {
+    *err = hipErrorInvalidValue;
+    return 0;
+  }
+  *err = hipGetLastError();
+  return rows * 5;  // four rows read and one written per output row
 }
 
 hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s) {

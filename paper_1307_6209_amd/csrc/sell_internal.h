@@ -210,6 +210,11 @@ hipError_t launch_crs(const int64_t *rpt, const int32_t *col, const double *val,
 // Bandwidth probes.
 hipError_t probe_read(const void *a, size_t bytes, double *sink, hipStream_t s);
 hipError_t probe_copy(const void *a, void *b, size_t bytes, hipStream_t s);
+hipError_t probe_write(void *a, size_t bytes, hipStream_t s);
+// Four random rows of row_bytes read per row written in order, over an input
+// of the largest power-of-two row count that fits in bytes and an output of
+// as many rows; returns the rows moved (read and written).
+int64_t probe_rows_write(const void *a, void *out, size_t bytes, int row_bytes, hipStream_t s, hipError_t *err);
 // Launches 2^27 random 8-byte gathers over the largest power-of-two prefix
 // of a (bytes); returns the gather count.
 int64_t probe_gather(const void *a, size_t bytes, double *sink, hipStream_t s, hipError_t *err);

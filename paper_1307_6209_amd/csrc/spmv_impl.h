@@ -761,11 +761,13 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   constexpr int SUB = RPW / 16;          // waves per unit
   constexpr int RPA = 64 / LPR;          // rows per access
   constexpr int RB = 16 / RPA;           // accesses (rows of a lane group) per wave
-  // chunk columns in flight: eight rows of X per lane for KV = 2, one
-  // column for KV = 4. Measured on the power-law 1M matrix: k = 16 (LPR 8)
-  // two columns 845 GF/s, four 1,055; k = 32 (LPR 16) two 997, four 925;
-  // k = 32 on the sigma = 1024 layout (LPR 8, KV 4) one 489, two 482.
-  constexpr int U = KV >= 4 ? 1 : 8 / RB;
+  // chunk columns in flight: four with 8 lanes per row and two right-hand
+  // sides per lane (k = 16), three with 16 lanes per row (k = 32), two for
+  // four right-hand sides per lane. Measured on the power-law 1M matrix at
+  // sigma = n: k = 16 two columns 845 GF/s, four 1,055; k = 32 two 996,
+  // three 1,099, four 1,008 (137 VGPRs, 3 waves per SIMD); k = 64 one
+  // 1,015, two 1,142; neutral on the sigma = 1024 layout.
+  constexpr int U = KV >= 4 ? 2 : (LPR == 16 ? 3 : 8 / RB);
   static_assert(RPW % 16 == 0, "blocks of 16 rows");
   using VecT = typename DVec<KV>::type;
 
@@ -832,22 +834,39 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
 #pragma unroll
         for (int v = 0; v < KV; ++v) acc[m][v] = __builtin_fma(vv[u][m], vget<KV>(xg[u][m], v), acc[m][v]);
   }
-  for (; j < je; ++j) {
-    int32_t ci[RB];
-    double vv[RB];
+  // the last je - j < U columns: one more round of the same shape, columns
+  // past the end read as padding (value 0, no gather), so that all their
+  // rows of X are in flight together (per column and per row group, a
+  // gather inside a branch with its multiply-add waited for each row in
+  // turn: most chunks of a power-law layout sorted by length are one to
+  // three columns wide, so most rows took that path)
+  if (j < je) {
+    int32_t ci[U][RB];
+    double vv[U][RB];
 #pragma unroll
-    for (int m = 0; m < RB; ++m) {
-      const int64_t o = (int64_t)j * C + RPA * m;
-      ci[m] = ld_col(colc + o);
-      vv[m] = ld_val(valc + o);
-    }
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int m = 0; m < RB; ++m)
-      if (vv[m] != 0.0) {
-        const VecT xg = *reinterpret_cast<const VecT *>(X + (int64_t)ci[m] * k + v0);
-#pragma unroll
-        for (int v = 0; v < KV; ++v) acc[m][v] = __builtin_fma(vv[m], vget<KV>(xg, v), acc[m][v]);
+      for (int m = 0; m < RB; ++m) {
+        const int64_t o = (int64_t)(j + u) * C + RPA * m;
+        ci[u][m] = 0;
+        vv[u][m] = 0.0;
+        if (j + u < je) {
+          ci[u][m] = ld_col(colc + o);
+          vv[u][m] = ld_val(valc + o);
+        }
       }
+    VecT xg[U][RB];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < RB; ++m)
+        xg[u][m] = vv[u][m] != 0.0 ? *reinterpret_cast<const VecT *>(X + (int64_t)ci[u][m] * k + v0) : VecT{};
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < RB; ++m)
+#pragma unroll
+        for (int v = 0; v < KV; ++v) acc[m][v] = __builtin_fma(vv[u][m], vget<KV>(xg[u][m], v), acc[m][v]);
   }
 #pragma unroll
   for (int m = 0; m < RB; ++m) {

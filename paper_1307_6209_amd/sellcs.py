@@ -495,7 +495,10 @@ def sell_batch_autotune(mats, C=(), sigma=(), val_dtype: str = "f64", acc_dtype:
 def sell_probe_bandwidth(kind: int, nbytes: int, reps: int = 10, stream=None) -> float:
     """Read-only (kind 0) or copy (kind 1) bandwidth in GB/s; kind 2: random
     8-byte gathers over an nbytes array, in gathered GB/s (8 B per gather);
-    kinds 3, 4, 5: random rows of 128, 256, 512 bytes, in GB/s of rows."""
+    kinds 3, 4, 5: random rows of 128, 256, 512 bytes, in GB/s of rows;
+    kind 6: write-only (16-byte non-temporal stores); kinds 7, 8, 9: rows of
+    128, 256, 512 bytes written in order, each the sum of four random rows
+    read, in GB/s of rows read and written."""
     g = c_d()
     _check(lib().sell_probe_bandwidth(kind, nbytes, reps, _stream(stream), ctypes.byref(g)), "sell_probe_bandwidth")
     return g.value

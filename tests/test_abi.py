@@ -98,7 +98,7 @@ def test_host_side_argument_errors(L):
     assert L.sell_batch_autotune(crs, 0, None, None, ctypes.byref(bt), sig) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_batch_autotune(crs, 1, None, None, None, sig) == sellcs.SELL_ERR_INVALID_ARG
     g = ctypes.c_double()
-    assert L.sell_probe_bandwidth(7, 1 << 30, 1, None, ctypes.byref(g)) == sellcs.SELL_ERR_INVALID_ARG
+    assert L.sell_probe_bandwidth(10, 1 << 30, 1, None, ctypes.byref(g)) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_autotune(None, 1, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_destroy(None) == sellcs.SELL_OK
     assert L.sell_batch_destroy(None) == sellcs.SELL_OK

@@ -11,9 +11,11 @@ def test_probes_plausible():
     from paper_1307_6209_amd import sellcs
     r = sellcs.sell_probe_bandwidth(0, 2 << 30, 5)
     c = sellcs.sell_probe_bandwidth(1, 2 << 30, 5)
-    say("read GB/s", r, "copy GB/s", c)
+    w = sellcs.sell_probe_bandwidth(6, 2 << 30, 5)
+    say("read GB/s", r, "copy GB/s", c, "write GB/s", w)
     assert 1000 < r < 8000 * 1.02
     assert 1000 < c < 8000 * 1.02
+    assert 1000 < w < 8000 * 1.02
 
 
 def test_gather_probe_plausible():
@@ -26,6 +28,16 @@ def test_gather_probe_plausible():
     say("gather GB/s (8 B per gather): 2 MiB", small, "2 GiB", big, "read", read)
     assert 0 < big < small
     assert big < read
+
+
+@pytest.mark.parametrize("kind", [3, 4, 5, 7, 8, 9])
+def test_row_probes_plausible(kind):
+    """Random rows (kinds 3-5) and random rows read with rows written (7-9)
+    over 256 MiB: positive, and neither beats 8 TB/s by more than rounding."""
+    from paper_1307_6209_amd import sellcs
+    g = sellcs.sell_probe_bandwidth(kind, 256 << 20, 3)
+    say("row probe", kind, "GB/s", g)
+    assert 100 < g < 8000 * 1.02
 
 
 def test_autotune_small():
