@@ -280,6 +280,30 @@ def read_write_bound(read_bytes, write_bytes, probes, sec, traffic=None) -> dict
     return out
 
 
+def block_ceiling(A, inf, k, t, probes) -> dict:
+    """Ceilings of the block form Y = A X (k = 16, 32, 64) from the probes,
+    against its measured time t. (1) One random row of X (8k bytes) per
+    nonzero at the random-row probe's rate over an array of X's size, the
+    matrix (12 B per slot, cl and cs, the permutation) at the read rate and
+    Y at the write rate, in turn. (2) The rows of X and Y at the rate of the
+    probe that mixes them (four random rows read per row written), the
+    matrix at the read rate."""
+    from paper_1307_6209_amd import sellcs
+    rows_pow2 = 1 << (A.nrows - 1).bit_length()
+    rows_gbs = sellcs.sell_probe_bandwidth({16: 3, 32: 4, 64: 5}[k], rows_pow2 * 8 * k, 5)
+    mixed_gbs = sellcs.sell_probe_bandwidth({16: 7, 32: 8, 64: 9}[k], rows_pow2 * 8 * k, 5)
+    mat = 12 * inf["padded"] + 12 * inf["nchunks"] + 4 * A.nrows
+    tc = (8.0 * k * A.nnz / (rows_gbs * 1e9) + mat / (probes["read_gbs"] * 1e9)
+          + 8.0 * k * A.nrows / (probes["write_gbs"] * 1e9))
+    tm = 8.0 * k * (A.nnz + A.nrows) / (mixed_gbs * 1e9) + mat / (probes["read_gbs"] * 1e9)
+    return {"rows_probe_gbs": round(rows_gbs, 1), "ceiling_us": round(tc * 1e6, 2),
+            "us": round(t * 1e6, 2), "frac": round(tc / t, 4),
+            "mixed_probe_gbs": round(mixed_gbs, 1),
+            "mixed_ceiling_us": round(tm * 1e6, 2), "frac_mixed": round(tm / t, 4),
+            "x_rows_per_s_g": round(A.nnz / t * 1e-9, 2),
+            "probe_rows_per_s_g": round(rows_gbs / (8.0 * k), 2)}
+
+
 def run_forms(args, probes, checks, checks_x) -> dict:
     import torch
     import numpy as np
@@ -305,7 +329,6 @@ def run_forms(args, probes, checks, checks_x) -> dict:
     A = synth.workload("powerlaw_1m")
     r, c, v = to_dev(A)
     spmmv, ceiling = {}, {}
-    rows_pow2 = 1 << (A.nrows - 1).bit_length()
     for C, sg in ((32, 1024), (32, A.nrows)):
         h = sellcs.sell_build(r, c, v, A.ncols, C, sg, kmax=64)
         inf = h.info
@@ -315,24 +338,7 @@ def run_forms(args, probes, checks, checks_x) -> dict:
             t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), max(10, args.steps // 10), 3)
             spmmv["C%d_sigma%d_k%d" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
             if sg == A.nrows and k in (16, 32, 64):
-                # one random row of X (8k bytes) per nonzero at the random-row
-                # probe's rate over an array of X's size, the matrix (12 B
-                # per slot, cl and cs, the permutation) at the read rate, and
-                # Y at the write rate, in turn
-                rows_gbs = sellcs.sell_probe_bandwidth({16: 3, 32: 4, 64: 5}[k], rows_pow2 * 8 * k, 5)
-                mat = 12 * inf["padded"] + 12 * inf["nchunks"] + 4 * A.nrows
-                tc = (8.0 * k * A.nnz / (rows_gbs * 1e9) + mat / (probes["read_gbs"] * 1e9)
-                      + 8.0 * k * A.nrows / (probes["write_gbs"] * 1e9))
-                # the same rows read and written at the rate of the probe
-                # that mixes them (four random rows read per row written)
-                mixed_gbs = sellcs.sell_probe_bandwidth({16: 7, 32: 8, 64: 9}[k], rows_pow2 * 8 * k, 5)
-                tm = 8.0 * k * (A.nnz + A.nrows) / (mixed_gbs * 1e9) + mat / (probes["read_gbs"] * 1e9)
-                ceiling["k%d" % k] = {"rows_probe_gbs": round(rows_gbs, 1), "ceiling_us": round(tc * 1e6, 2),
-                                      "us": round(t * 1e6, 2), "frac": round(tc / t, 4),
-                                      "mixed_probe_gbs": round(mixed_gbs, 1),
-                                      "mixed_ceiling_us": round(tm * 1e6, 2), "frac_mixed": round(tm / t, 4),
-                                      "x_rows_per_s_g": round(A.nnz / t * 1e-9, 2),
-                                      "probe_rows_per_s_g": round(rows_gbs / (8.0 * k), 2)}
+                ceiling["k%d" % k] = block_ceiling(A, inf, k, t, probes)
             if sg == A.nrows and k in (1, 8, 32):
                 t = cold_time(lambda: sellcs.sell_spmmv(h, X, Y), flush)
                 spmmv["C%d_sigma%d_k%d_cold" % (C, sg, k)] = round(2.0 * A.nnz * k / t * 1e-9, 2)
@@ -542,11 +548,18 @@ def block_pass(args):
             t = time_calls(lambda: sellcs.sell_spmmv(h, X, Y), 50, 5)
         rows.append({"k": k, "us": round(t * 1e6, 2), "gfs": round(2.0 * A.nnz * k / t * 1e-9, 2)})
         del X, Y
+    probes = None
     if args.pmc_pass:
         sellcs.sell_probe_bandwidth(1, 1 << 30, 1)
         torch.cuda.synchronize()
+    else:
+        probes = {"read_gbs": round(sellcs.sell_probe_bandwidth(0, 4 << 30, 10), 1),
+                  "write_gbs": round(sellcs.sell_probe_bandwidth(6, 4 << 30, 10), 1)}
+        for row in rows:
+            row["ceiling"] = block_ceiling(A, inf, row["k"], row["us"] * 1e-6, probes)
     print(json.dumps({"block_pass": "powerlaw_1m", "C": 32, "sigma": A.nrows, "n": A.nrows, "nnz": A.nnz,
-                      "padded": inf["padded"], "beta": inf["beta"], "nsplit": inf["nsplit"], "rows": rows}))
+                      "padded": inf["padded"], "beta": inf["beta"], "nsplit": inf["nsplit"], "probes": probes,
+                      "rows": rows}))
 
 
 def batch_pass(args):

@@ -89,14 +89,17 @@ hipError_t launch_spmmv_rows(int C, int LPR, const SpmvArgs &a, hipStream_t s) {
   const int rpw = C < 64 ? C : 64;
   const int64_t waves = a.nwork * (rpw / 16);  // 16 rows per wave
   const unsigned nb = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  const unsigned ncomb = (unsigned)std::min(512, rpw * a.k);  // threads per combined slice
+  // threads per block of a combined slice, and blocks per slice: one
+  // thread per (row, right-hand side)
+  const unsigned ncomb = (unsigned)std::min(512, rpw * a.k);
+  const unsigned nzc = (unsigned)((rpw * a.k + (int)ncomb - 1) / (int)ncomb);
   const int KV = a.k / LPR;
 #define SELL_L(CC, LL, KK)                                                                                   \
   if (C == CC && LPR == LL && KV == KK) {                                                                   \
     hipLaunchKernelGGL((dev::k_spmmv_rows<CC, LL, KK>), dim3(nb), dim3(64 * kWavesPerBlock), 0, s, a); \
     hipError_t e_ = hipGetLastError();                                                                      \
     if (e_ != hipSuccess || a.nsplit == 0) return e_;                                                       \
-    hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, 1), dim3(ncomb), 0, s, a);       \
+    hipLaunchKernelGGL((dev::k_combine_mm<CC>), dim3((unsigned)a.nsplit, 1, nzc), dim3(ncomb), 0, s, a);  \
     return hipGetLastError();                                                                               \
   }
 #define SELL_LC(LL, KK) SELL_L(16, LL, KK) SELL_L(32, LL, KK) SELL_L(64, LL, KK) SELL_L(128, LL, KK)

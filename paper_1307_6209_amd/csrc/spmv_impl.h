@@ -473,16 +473,17 @@ __device__ __forceinline__ void combine_split(const SplitDesc d, const int32_t *
   const int64_t p = chunk * C + h * RPW + lane;
   if (p >= nrows) return;
   const A *part = static_cast<const A *>(partial) + d.poff + lane;
+  // sixteen loads in flight, added in order; the last round reads +0 past
+  // the last segment (adding +0 leaves every sum but -0 unchanged, and -0
+  // only turns into +0), so that it too is one round trip
   A sum = 0;
-  int q = 0;
-  for (; q + 8 <= d.nseg; q += 8) {  // eight loads in flight, added in order
-    A t[8];
+  for (int q = 0; q < d.nseg; q += 16) {
+    A t[16];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) t[e] = part[(int64_t)(q + e) * RPW];
+    for (int e = 0; e < 16; ++e) t[e] = q + e < d.nseg ? part[(int64_t)(q + e) * RPW] : (A)0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sum += t[e];
+    for (int e = 0; e < 16; ++e) sum += t[e];
   }
-  for (; q < d.nseg; ++q) sum += part[(int64_t)q * RPW];
   const int64_t row = perm ? (int64_t)perm[p] : p;
   static_cast<A *>(yv)[row] = sum;
 }
@@ -888,10 +889,12 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   }
 }
 
-// Block form: add the segment sums of split row slices. Block (w, tile):
-// split slice w, pass tile; one thread per (row, right-hand side) of the
-// slice (RPW * KT = 64 * KV threads), the segment sums added in segment
-// order with eight loads in flight.
+// Block form: add the segment sums of split row slices. Block (w, tile, z):
+// split slice w, pass tile, z-th part of the slice's (row, right-hand side)
+// elements; one thread per element where the grid covers them all, the
+// segment sums added in segment order with sixteen loads in flight (the
+// longest slices have tens of segments, and each round trip to them is a
+// separate latency: the combining is latency-bound).
 template <int C>
 __global__ void __launch_bounds__(512) k_combine_mm(SpmvArgs a) {
   constexpr int RPW = C < 64 ? C : 64;
@@ -902,7 +905,8 @@ __global__ void __launch_bounds__(512) k_combine_mm(SpmvArgs a) {
   const int h = d.item - (int)(chunk * WPC);
   const double *base = static_cast<const double *>(a.partial) + (d.poff * ntiles + (int64_t)tile * d.nseg * RPW) * KT;
   double *Y = static_cast<double *>(a.y);
-  for (int e = threadIdx.x; e < RPW * KT; e += blockDim.x) {
+  // blockIdx.z: which part of the slice's elements this block adds
+  for (int e = blockIdx.z * blockDim.x + threadIdx.x; e < RPW * KT; e += gridDim.z * blockDim.x) {
     const int rl = e / KT, vl = e - rl * KT;
     const int v = tile * KT + vl;
     const int64_t p = chunk * C + h * RPW + rl;
@@ -910,15 +914,13 @@ __global__ void __launch_bounds__(512) k_combine_mm(SpmvArgs a) {
     const double *src = base + (int64_t)rl * KT + vl;
     const int64_t step = (int64_t)RPW * KT;  // between the sums of two segments
     double sum = 0.0;
-    int q = 0;
-    for (; q + 8 <= d.nseg; q += 8) {
-      double t[8];
+    for (int q = 0; q < d.nseg; q += 16) {  // +0 past the last segment, as in combine_split
+      double t[16];
 #pragma unroll
-      for (int e8 = 0; e8 < 8; ++e8) t[e8] = src[(int64_t)(q + e8) * step];
+      for (int e8 = 0; e8 < 16; ++e8) t[e8] = q + e8 < d.nseg ? src[(int64_t)(q + e8) * step] : 0.0;
 #pragma unroll
-      for (int e8 = 0; e8 < 8; ++e8) sum += t[e8];
+      for (int e8 = 0; e8 < 16; ++e8) sum += t[e8];
     }
-    for (; q < d.nseg; ++q) sum += src[(int64_t)q * step];
     const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
     Y[row * k + v] = sum;
   }
