@@ -652,6 +652,15 @@ def main():
             for mib in (4, 16, 64, 128, 256, 512, 1024, 4096):
                 g = sellcs.sell_probe_bandwidth(kind, mib << 20, 5)
                 res["rows%d_%dmib_grows_per_s" % (rb, mib)] = round(g / rb, 2)
+        # four random rows read per row written in order (the block form's
+        # mix), in G rows/s read and written
+        for kind, rb in ((7, 128), (8, 256), (9, 512)):
+            for mib in (64, 128, 256, 512, 1024):
+                g = sellcs.sell_probe_bandwidth(kind, mib << 20, 5)
+                res["rows%d_mixed_%dmib_grows_per_s" % (rb, mib)] = round(g / rb, 2)
+        # write-only and copy streams over 4 GiB
+        res["write_4gib_gbs"] = round(sellcs.sell_probe_bandwidth(6, 4 << 30, 10), 1)
+        res["copy_4gib_gbs"] = round(sellcs.sell_probe_bandwidth(1, 4 << 30, 10), 1)
         print(json.dumps({"probe_sweep": res}))
         return
     A = synth.workload(HEADLINE["workload"])
