@@ -800,7 +800,7 @@ def main():
     # SELL-32-1 against SELL-32-sigma autotuned over sigma = 2^0 .. 2^17 and n, unroll and x path
     sig_space = tuple(1 << i for i in range(18)) + (A.nrows,)
     tuned = sellcs.sell_autotune(r, c, v, A.ncols, k=1, C=(32,), sigma=sig_space, unroll=(4, 8, 16), xwindow=(-1, 0),
-                                 reps=20)
+                                 xwindow_chunks=(4, 8), reps=20)
     line["autotuned_stencil27_160"] = {key: (round(val, 3) if isinstance(val, float) else val)
                                        for key, val in tuned.items()}
     h.close()

@@ -350,6 +350,9 @@ typedef struct {
                              best */
   const int32_t *xwindow; int32_t nxwindow; /* x path: the xwindow build option (0 = LDS
                                                window when it fits, -1 = L2 gathers) */
+  const int32_t *xwindow_chunks; int32_t nxwindow_chunks; /* waves per workgroup of the window
+                                               product: the xwindow_chunks build option
+                                               (0 = automatic, 4, 8); NULL/0: {0} */
 } sell_tune_space;
 
 typedef struct {
@@ -365,6 +368,7 @@ typedef struct {
   int32_t candidates;   /* configurations measured */
   int32_t predicted;    /* configurations ranked by the model (model_guided > 0) */
   int32_t xwindow;      /* 1 when the fastest product staged x windows in LDS */
+  int32_t xwindow_chunks; /* its chunks (waves) per window workgroup; 0 without window */
 } sell_tuned;
 
 /*

@@ -1133,6 +1133,8 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   const int32_t defX[] = {0};
   const int32_t *Xs = sp.nxwindow > 0 ? sp.xwindow : defX;
   int nX = sp.nxwindow > 0 ? sp.nxwindow : 1;
+  const int32_t *Ws = sp.nxwindow_chunks > 0 ? sp.xwindow_chunks : defX;
+  int nW = sp.nxwindow_chunks > 0 ? sp.nxwindow_chunks : 1;
   sell_build_opts o{};
   o.val_dtype = sp.val_dtype;
   o.acc_dtype = sp.acc_dtype;
@@ -1193,17 +1195,24 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   r.gflops = -1.0;
   int cands = 0;
   for (const auto &cand : order) {
-    for (int iv = 0; iv < nV * nG * nX; ++iv) {
+    for (int iv = 0; iv < nV * nG * nX * nW; ++iv) {
       const int ic = cand.first, is = cand.second;
-      // slots per lane, split width and x path are build parameters: one
-      // build each
+      // slots per lane, split width, x path and window workgroup size are
+      // build parameters: one build each
       o.vec = Vs[iv % nV];
       o.seg_cols = Gs[(iv / nV) % nG];
-      o.xwindow = Xs[iv / (nV * nG)];
+      o.xwindow = Xs[(iv / (nV * nG)) % nX];
+      o.xwindow_chunks = Ws[iv / (nV * nG * nX)];
       sell_handle h = nullptr;
       sell_status st = sell_build(A, Cs[ic], Ss[is], &o, stream, &h);
       if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
       if (st != SELL_OK) return st;
+      // without a window the size does not change the product: time it for
+      // the first size of the list only
+      if (!h->lcol && iv / (nV * nG * nX) > 0) {
+        sell_destroy(h);
+        continue;
+      }
       for (int iu = 0; iu < nU; ++iu) {
         if (Us[iu] != 4 && Us[iu] != 8 && Us[iu] != 16) continue;
         // sixteen slots in flight: only the window kernel with two per lane
@@ -1235,6 +1244,7 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
             r.unroll = Us[iu];
             r.ktile = h->ktile;
             r.xwindow = h->lcol ? 1 : 0;
+            r.xwindow_chunks = h->lcol ? h->xw_gc : 0;
             r.gflops = gf;
             r.us_per_call = t * 1e6;
             r.beta = h->beta;

@@ -60,14 +60,15 @@ class SellTuneSpace(ctypes.Structure):
                 ("nktile", c_i32), ("vec", ctypes.POINTER(c_i32)), ("nvec", c_i32),
                 ("seg_cols", ctypes.POINTER(c_i32)), ("nseg_cols", c_i32), ("val_dtype", ctypes.c_int),
                 ("acc_dtype", ctypes.c_int), ("reps", c_i32), ("model_guided", c_i32),
-                ("xwindow", ctypes.POINTER(c_i32)), ("nxwindow", c_i32)]
+                ("xwindow", ctypes.POINTER(c_i32)), ("nxwindow", c_i32),
+                ("xwindow_chunks", ctypes.POINTER(c_i32)), ("nxwindow_chunks", c_i32)]
 
 
 class SellTuned(ctypes.Structure):
     _fields_ = [("C", c_i32), ("sigma", c_i64), ("unroll", c_i32), ("ktile", c_i32), ("vec", c_i32),
                 ("seg_cols", c_i32), ("gflops", c_d),
                 ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32), ("predicted", c_i32),
-                ("xwindow", c_i32)]
+                ("xwindow", c_i32), ("xwindow_chunks", c_i32)]
 
 
 class SellBatchTuned(ctypes.Structure):
@@ -443,7 +444,7 @@ def sell_batch_destroy(b: SellBatch):
 
 def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=(), ktile=(), vec=(), seg_cols=(),
                   val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0, model_guided: int = 0,
-                  xwindow=(), stream=None) -> dict:
+                  xwindow=(), stream=None, xwindow_chunks=()) -> dict:
     """Time the configurations of the search space (all of them, or the
     model_guided best by the code-balance model); return the fastest."""
     import torch
@@ -456,9 +457,10 @@ def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=
     arrs = [(c_i32 * len(C))(*C), (c_i64 * len(sigma))(*sigma), (c_i32 * len(unroll))(*unroll),
             (c_i32 * len(ktile))(*ktile), (c_i32 * len(vec))(*vec), (c_i32 * len(seg_cols))(*seg_cols)]
     xa = (c_i32 * len(xwindow))(*xwindow)
+    wa = (c_i32 * len(xwindow_chunks))(*xwindow_chunks)
     sp = SellTuneSpace(arrs[0], len(C), arrs[1], len(sigma), arrs[2], len(unroll), arrs[3], len(ktile),
                        arrs[4], len(vec), arrs[5], len(seg_cols), DTYPES[val_dtype], DTYPES[acc_dtype], reps,
-                       model_guided, xa, len(xwindow))
+                       model_guided, xa, len(xwindow), wa, len(xwindow_chunks))
     r = SellTuned()
     _check(lib().sell_autotune(ctypes.byref(A), k, ctypes.byref(sp), _stream(stream), ctypes.byref(r)), "sell_autotune")
     return {name: getattr(r, name) for name, _ in SellTuned._fields_}

@@ -141,3 +141,18 @@ def test_autotune_x_path():
     r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(32,), sigma=(1,), unroll=(8,), xwindow=(-1, 0), reps=10)
     say("autotune x path", r)
     assert r["candidates"] == 2 and r["xwindow"] in (0, 1)
+
+
+def test_autotune_window_workgroup_size():
+    """The window product's workgroup size (4 or 8 chunks, one wave each) is
+    searched too: every window size is timed once, the global-index product
+    once (the size does not change it), and the result names the size of
+    the window that won."""
+    from paper_1307_6209_amd import sellcs
+    A = synth.stencil27(64)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(32,), sigma=(1,), unroll=(8,), xwindow=(-1, 0),
+                             xwindow_chunks=(4, 8), reps=10)
+    say("autotune window workgroup size", r)
+    assert r["candidates"] == 3
+    assert (r["xwindow"], r["xwindow_chunks"]) in ((0, 0), (1, 4), (1, 8))
