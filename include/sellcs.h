@@ -83,7 +83,7 @@ typedef struct {
                            a multiple of 64): 0 auto, < 0 never split */
   int32_t ktile;        /* right-hand sides per pass in sell_spmmv: 0 auto, else a
                            power of two <= 64. Auto with k = 16, 32 or 64 (C >= 16,
-                           X and Y aligned to k/LPR doubles) runs one pass with 8
+                           X and Y aligned to 16 bytes) runs one pass with 8
                            or 16 lanes (LPR) per row, each reading k/LPR
                            right-hand sides, chosen by k and the layout's beta */
   int32_t kmax;         /* largest k sell_spmmv will be called with on matrices

@@ -639,8 +639,8 @@ sell_status spmmv_run(sell_handle h, const void *X, void *Y, int32_t k, void *st
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, w + ": C must be >= 8 for k > 1");
   if (!scratch && h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, w + ": k exceeds the kmax given at build");
   // With the automatic pass width, k = 16, 32 and 64 run in one pass with
-  // LPR lanes per row: each row of X is read whole by one access (X and Y
-  // aligned to the k/LPR doubles of a lane). More lanes per row suit dense
+  // LPR lanes per row: each row of X is read whole by one or two accesses of
+  // 16 bytes per lane (X and Y aligned to 16 bytes). More lanes per row suit dense
   // layouts, fewer (or the pass kernel) padding-heavy ones, whose matrix
   // stream the lanes of a row read through broadcasts. Measured on the
   // power-law 1M matrix at beta = 0.98 (sigma = n) / 0.14 (sigma = 1024),
@@ -651,7 +651,7 @@ sell_status spmmv_run(sell_handle h, const void *X, void *Y, int32_t k, void *st
     const bool dense = h->beta >= 0.5;
     const int lpr = k == 64 ? 16 : k == 32 ? (dense ? 16 : 8) : (k == 16 && dense) ? 8 : 0;
     if (h->ktile == 0 && lpr > 0 && h->C >= 16 &&
-        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % (sizeof(double) * (k / lpr))) == 0) {
+        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % 16) == 0) {
       if (scratch && partial_doubles(h, k, k) * (int64_t)sizeof(double) > (int64_t)scratch_bytes)
         return too_big(partial_doubles(h, k, k));
       sell::SpmvArgs a = args_of(h, X, Y);

@@ -747,10 +747,43 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   }
 }
 
+// The KV right-hand sides of a lane of the one-pass block kernel, as 16-byte
+// pairs: pair p of lane q of a row holds right-hand sides p*2*LPR + 2q and
+// the next, so that one 16-byte access of the LPR lanes of a row covers
+// 32*LPR contiguous bytes of it (KV contiguous values per lane would make
+// each 16-byte access cover every other 16 bytes of a span twice as long).
+// p points at the lane's first pair.
+template <int LPR, int KV>
+__device__ __forceinline__ typename DVec<KV>::type ld_rhs(const double *p) {
+  typedef double P2 __attribute__((ext_vector_type(2)));
+  typename DVec<KV>::type r;
+#pragma unroll
+  for (int q = 0; q < KV / 2; ++q) {
+    const P2 t = *reinterpret_cast<const P2 *>(p + q * 2 * LPR);
+    r[2 * q] = t[0];
+    r[2 * q + 1] = t[1];
+  }
+  return r;
+}
+
+template <int LPR, int KV>
+__device__ __forceinline__ void st_rhs(const typename DVec<KV>::type &o, double *p, bool nontemporal) {
+  typedef double P2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int q = 0; q < KV / 2; ++q) {
+    P2 t;
+    t[0] = o[2 * q];
+    t[1] = o[2 * q + 1];
+    if (nontemporal) __builtin_nontemporal_store(t, reinterpret_cast<P2 *>(p + q * 2 * LPR));
+    else *reinterpret_cast<P2 *>(p + q * 2 * LPR) = t;
+  }
+}
+
 // Block form for k = LPR * KV right-hand sides: LPR lanes share a row (8 or
-// 16), lane q of a row holding right-hand sides q*KV .. q*KV+KV-1, so the k
-// values of one row of X are read by one access of LPR lanes and a wave
-// covers 64/LPR rows per access. Work units and the partial-sum layout are
+// 16), lane q of a row holding the KV/2 pairs of right-hand sides
+// p*2*LPR + 2q, p*2*LPR + 2q + 1 (ld_rhs), so the k values of one row of X
+// are read by KV/2 accesses of LPR lanes, each over 32*LPR contiguous bytes,
+// and a wave covers 64/LPR rows per access. Work units and the partial-sum layout are
 // those of k_spmmv with a single pass of width k; each unit (rpw rows of a
 // chunk) is shared by rpw/16 waves of 16 rows each, which walk the unit's
 // chunk columns with U columns in flight; each slot is read once. Per row
@@ -789,7 +822,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
     item = (int32_t)w;
   }
   const int k = a.k;  // LPR * KV
-  const int gq = lane / LPR, v0 = (lane % LPR) * KV;
+  const int gq = lane / LPR, v0 = 2 * (lane % LPR);  // first right-hand side of this lane
   const int64_t chunk = item / WPC;
   const int h = item - (int)(chunk * WPC);
   const int64_t base = a.cs[chunk];
@@ -827,7 +860,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int m = 0; m < RB; ++m)
-        xg[u][m] = vv[u][m] != 0.0 ? *reinterpret_cast<const VecT *>(X + (int64_t)ci[u][m] * k + v0) : VecT{};
+        xg[u][m] = vv[u][m] != 0.0 ? ld_rhs<LPR, KV>(X + (int64_t)ci[u][m] * k + v0) : VecT{};
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -861,7 +894,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int m = 0; m < RB; ++m)
-        xg[u][m] = vv[u][m] != 0.0 ? *reinterpret_cast<const VecT *>(X + (int64_t)ci[u][m] * k + v0) : VecT{};
+        xg[u][m] = vv[u][m] != 0.0 ? ld_rhs<LPR, KV>(X + (int64_t)ci[u][m] * k + v0) : VecT{};
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -878,13 +911,13 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
       const int64_t p = chunk * C + h * RPW + rl;
       if (p < a.nrows) {
         const int64_t row = a.perm ? (int64_t)a.perm[p] : p;
-        __builtin_nontemporal_store(o, reinterpret_cast<VecT *>(Y + row * k + v0));
+        st_rhs<LPR, KV>(o, Y + row * k + v0, true);
       }
     } else {
       // partial[(poff + seg*RPW + rl)*k + v]: the layout of k_spmmv with one
       // pass of width k
       double *mine = static_cast<double *>(a.partial) + ((poff + (int64_t)seg * RPW + rl) * k + v0);
-      *reinterpret_cast<VecT *>(mine) = o;
+      st_rhs<LPR, KV>(o, mine, false);
     }
   }
 }

@@ -157,3 +157,25 @@ def test_spmmv_explicit_zero_entries(k, ktile, sigma):
     check(B, Y, X)
     allzero = np.array([not np.any(~zero[A.rpt[i]:A.rpt[i + 1]]) for i in range(A.nrows)])
     assert np.all(Y[allzero] == 0.0)
+
+
+@pytest.mark.parametrize("k", [32, 64])
+def test_spmmv_rows_kernel_16_byte_aligned(k):
+    """X and Y 16 bytes off a 32-byte boundary: the one-pass kernel reads and
+    writes 16-byte pairs of right-hand sides, so it still runs; the result
+    equals the aligned call's bit for bit and the oracle within its bound."""
+    import torch
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(20_000, seed=55)
+    X = synth.block_vector(A.ncols, k, seed=56)
+    h = build(A, 32, A.nrows, kmax=64)
+    Xb = torch.zeros(A.ncols * k + 2, dtype=torch.float64, device="cuda")
+    Xb[2:] = torch.from_numpy(X.ravel()).cuda()
+    Yb = torch.zeros(A.nrows * k + 2, dtype=torch.float64, device="cuda")
+    Xv, Yv = Xb[2:].view(A.ncols, k), Yb[2:].view(A.nrows, k)
+    assert Xv.data_ptr() % 32 == 16 and Yv.data_ptr() % 32 == 16
+    sellcs.sell_spmmv(h, Xv, Yv)
+    torch.cuda.synchronize()
+    Y = Yv.cpu().numpy()
+    check(A, Y, X)
+    assert np.array_equal(Y, run_spmmv(h, X))
