@@ -78,8 +78,8 @@ def test_one_unit_per_wave(driver, seed, nmats):
     # the load reported per XCD is the cost of the units placed there
     for x in range(X):
         assert res["load"][x] == cost_a[xcd == x].sum()
-    # a matrix no larger than a 32nd of the batch runs on one XCD
-    cap = max(1, cost_a.sum() // (4 * X))
+    # a matrix no larger than a 16th of the batch runs on one XCD
+    cap = max(1, cost_a.sum() // (2 * X))
     for m in range(nmats):
         sel = mat_a == m
         if sel.any() and cost_a[sel].sum() <= cap:
