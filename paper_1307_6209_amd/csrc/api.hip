@@ -647,9 +647,12 @@ sell_status spmmv_run(sell_handle h, const void *X, void *Y, int32_t k, void *st
   // GF/s: k = 16 LPR 8 843 / 366, pass kernel 756 / 385; k = 32 LPR 16 997 /
   // 410, LPR 8 835 / 477, pass kernel 862 / 402; k = 64 LPR 16 1013 / 543,
   // pass kernel 913 / 421; k = 8 LPR 8 457 / 191, pass kernel 461 / 256.
+  // With the 16-byte pairs of right-hand sides: k = 64 LPR 8 1,296 / 586
+  // against LPR 16 1,229 / 564; k = 32 LPR 8 1,086 against LPR 16 1,132
+  // at sigma = n.
   {
     const bool dense = h->beta >= 0.5;
-    const int lpr = k == 64 ? 16 : k == 32 ? (dense ? 16 : 8) : (k == 16 && dense) ? 8 : 0;
+    const int lpr = k == 64 ? 8 : k == 32 ? (dense ? 16 : 8) : (k == 16 && dense) ? 8 : 0;
     if (h->ktile == 0 && lpr > 0 && h->C >= 16 &&
         ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % 16) == 0) {
       if (scratch && partial_doubles(h, k, k) * (int64_t)sizeof(double) > (int64_t)scratch_bytes)

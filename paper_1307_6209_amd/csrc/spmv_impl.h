@@ -796,12 +796,15 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   constexpr int RPA = 64 / LPR;          // rows per access
   constexpr int RB = 16 / RPA;           // accesses (rows of a lane group) per wave
   // chunk columns in flight: four with 8 lanes per row and two right-hand
-  // sides per lane (k = 16), three with 16 lanes per row (k = 32), two for
-  // four right-hand sides per lane. Measured on the power-law 1M matrix at
-  // sigma = n: k = 16 two columns 845 GF/s, four 1,055; k = 32 two 996,
-  // three 1,099, four 1,008 (137 VGPRs, 3 waves per SIMD); k = 64 one
-  // 1,015, two 1,142; neutral on the sigma = 1024 layout.
-  constexpr int U = KV >= 4 ? 2 : (LPR == 16 ? 3 : 8 / RB);
+  // sides per lane (k = 16), three with 16 lanes per row (k = 32), two with
+  // 16 lanes and four right-hand sides per lane, three with 8 lanes and four
+  // or eight. Measured on the power-law 1M matrix at sigma = n: k = 16 two
+  // columns 845 GF/s, four 1,055; k = 32 two 996, three 1,099, four 1,008
+  // (137 VGPRs, 3 waves per SIMD); k = 64 with 16 lanes per row one 1,015,
+  // two 1,142; with 8 lanes per row one 1,167, two 1,299, three 1,288, four
+  // 1,228 (sigma = 1024: 607, 585, 677, 574); k = 32 with 8 lanes per row on
+  // the sigma = 1024 layout two 488, three 506; otherwise neutral there.
+  constexpr int U = KV >= 8 ? 3 : KV >= 4 ? (LPR == 8 ? 3 : 2) : (LPR == 16 ? 3 : 8 / RB);
   static_assert(RPW % 16 == 0, "blocks of 16 rows");
   using VecT = typename DVec<KV>::type;
 
