@@ -638,21 +638,20 @@ sell_status spmmv_run(sell_handle h, const void *X, void *Y, int32_t k, void *st
   }
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, w + ": C must be >= 8 for k > 1");
   if (!scratch && h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, w + ": k exceeds the kmax given at build");
-  // With the automatic pass width, k = 16, 32 and 64 run in one pass with
-  // LPR lanes per row: each row of X is read whole by one or two accesses of
-  // 16 bytes per lane (X and Y aligned to 16 bytes). More lanes per row suit dense
-  // layouts, fewer (or the pass kernel) padding-heavy ones, whose matrix
-  // stream the lanes of a row read through broadcasts. Measured on the
-  // power-law 1M matrix at beta = 0.98 (sigma = n) / 0.14 (sigma = 1024),
-  // GF/s: k = 16 LPR 8 843 / 366, pass kernel 756 / 385; k = 32 LPR 16 997 /
-  // 410, LPR 8 835 / 477, pass kernel 862 / 402; k = 64 LPR 16 1013 / 543,
-  // pass kernel 913 / 421; k = 8 LPR 8 457 / 191, pass kernel 461 / 256.
-  // With the 16-byte pairs of right-hand sides: k = 64 LPR 8 1,296 / 586
-  // against LPR 16 1,229 / 564; k = 32 LPR 8 1,086 against LPR 16 1,132
-  // at sigma = n.
+  // With the automatic pass width, k = 16, 32 and 64 run in one pass with 8
+  // lanes per row: each row of X is read whole by k/16 accesses of 16 bytes
+  // per lane (X and Y aligned to 16 bytes); k = 16 on padding-heavy layouts
+  // runs the pass kernel, whose lanes do not share the matrix stream through
+  // broadcasts. Measured on the power-law 1M matrix at beta = 0.98 (sigma = n)
+  // / 0.14 (sigma = 1024), GF/s, with the right-hand sides as 16-byte pairs
+  // and the columns in flight of k_spmmv_rows: k = 16 8 lanes 1,097 / 366
+  // (before the pairs), pass kernel 756 / 405; k = 32 8 lanes 1,214 / 505,
+  // 16 lanes 1,131 / 410 (before the pairs), pass kernel 862 / 402; k = 64
+  // 8 lanes 1,296 / 677, 16 lanes 1,229 / 564, pass kernel 913 / 421; k = 8
+  // 8 lanes 457 / 191, 4 lanes 626, pass kernel 686 / 293.
   {
     const bool dense = h->beta >= 0.5;
-    const int lpr = k == 64 ? 8 : k == 32 ? (dense ? 16 : 8) : (k == 16 && dense) ? 8 : 0;
+    const int lpr = (k == 64 || k == 32 || (k == 16 && dense)) ? 8 : 0;
     if (h->ktile == 0 && lpr > 0 && h->C >= 16 &&
         ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % 16) == 0) {
       if (scratch && partial_doubles(h, k, k) * (int64_t)sizeof(double) > (int64_t)scratch_bytes)

@@ -779,8 +779,8 @@ __device__ __forceinline__ void st_rhs(const typename DVec<KV>::type &o, double 
   }
 }
 
-// Block form for k = LPR * KV right-hand sides: LPR lanes share a row (8 or
-// 16), lane q of a row holding the KV/2 pairs of right-hand sides
+// Block form for k = LPR * KV right-hand sides: LPR lanes share a row (8;
+// 16 measured slower), lane q of a row holding the KV/2 pairs of right-hand sides
 // p*2*LPR + 2q, p*2*LPR + 2q + 1 (ld_rhs), so the k values of one row of X
 // are read by KV/2 accesses of LPR lanes, each over 32*LPR contiguous bytes,
 // and a wave covers 64/LPR rows per access. Work units and the partial-sum layout are
@@ -802,8 +802,9 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   // columns 845 GF/s, four 1,055; k = 32 two 996, three 1,099, four 1,008
   // (137 VGPRs, 3 waves per SIMD); k = 64 with 16 lanes per row one 1,015,
   // two 1,142; with 8 lanes per row one 1,167, two 1,299, three 1,288, four
-  // 1,228 (sigma = 1024: 607, 585, 677, 574); k = 32 with 8 lanes per row on
-  // the sigma = 1024 layout two 488, three 506; otherwise neutral there.
+  // 1,228 (sigma = 1024: 607, 585, 677, 574); k = 32 with 8 lanes per row
+  // three 1,214 (sigma = 1024: two 488, three 506, four 486); otherwise
+  // neutral on the sigma = 1024 layout.
   constexpr int U = KV >= 8 ? 3 : KV >= 4 ? (LPR == 8 ? 3 : 2) : (LPR == 16 ? 3 : 8 / RB);
   static_assert(RPW % 16 == 0, "blocks of 16 rows");
   using VecT = typename DVec<KV>::type;
