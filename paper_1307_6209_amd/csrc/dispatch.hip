@@ -103,7 +103,7 @@ hipError_t launch_spmmv_rows(int C, int LPR, const SpmvArgs &a, hipStream_t s) {
     return hipGetLastError();                                                                               \
   }
 #define SELL_LC(LL, KK) SELL_L(16, LL, KK) SELL_L(32, LL, KK) SELL_L(64, LL, KK) SELL_L(128, LL, KK)
-  SELL_LC(8, 2) SELL_LC(8, 4) SELL_LC(8, 8)
+  SELL_LC(4, 4) SELL_LC(8, 4) SELL_LC(8, 8)
 #undef SELL_LC
 #undef SELL_L
   return hipErrorInvalidValue;

@@ -163,8 +163,8 @@ enum DtypeCombo {
 // skip_zero: slots holding value 0 skip their gather (for padding-heavy layouts).
 hipError_t launch_spmv(int combo, int C, int U, int V, bool skip_zero, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_spmmv(int C, int KV, const SpmvArgs &a, hipStream_t s);
-// Block form with LPR lanes per row (LPR 8: k = 16, 32 or 64; C >= 16): one
-// pass, a.kt == a.k.
+// Block form with LPR lanes per row (LPR 4: k = 16; LPR 8: k = 32 or 64;
+// C >= 16): one pass, a.kt == a.k.
 hipError_t launch_spmmv_rows(int C, int LPR, const SpmvArgs &a, hipStream_t s);
 // Product with the x window staged in LDS (C in 8..64, V 1 or 2, no split
 // chunks); lds_bytes: the largest window times the x element size, rounded

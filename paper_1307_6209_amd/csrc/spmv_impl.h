@@ -779,8 +779,8 @@ __device__ __forceinline__ void st_rhs(const typename DVec<KV>::type &o, double 
   }
 }
 
-// Block form for k = LPR * KV right-hand sides: LPR lanes share a row (8;
-// 16 measured slower), lane q of a row holding the KV/2 pairs of right-hand sides
+// Block form for k = LPR * KV right-hand sides: LPR lanes share a row (4 or
+// 8; 16 measured slower), lane q of a row holding the KV/2 pairs of right-hand sides
 // p*2*LPR + 2q, p*2*LPR + 2q + 1 (ld_rhs), so the k values of one row of X
 // are read by KV/2 accesses of LPR lanes, each over 32*LPR contiguous bytes,
 // and a wave covers 64/LPR rows per access. Work units and the partial-sum layout are
@@ -803,9 +803,10 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv_rows(SpmvArgs a) 
   // (137 VGPRs, 3 waves per SIMD); k = 64 with 16 lanes per row one 1,015,
   // two 1,142; with 8 lanes per row one 1,167, two 1,299, three 1,288, four
   // 1,228 (sigma = 1024: 607, 585, 677, 574); k = 32 with 8 lanes per row
-  // three 1,214 (sigma = 1024: two 488, three 506, four 486); otherwise
-  // neutral on the sigma = 1024 layout.
-  constexpr int U = KV >= 8 ? 3 : KV >= 4 ? (LPR == 8 ? 3 : 2) : (LPR == 16 ? 3 : 8 / RB);
+  // three 1,214 (sigma = 1024: two 488, three 506, four 486); k = 16 with 4
+  // lanes per row three 1,061, four 1,124-1,132, six 1,113, eight 1,039;
+  // otherwise neutral on the sigma = 1024 layout.
+  constexpr int U = KV >= 8 ? 3 : KV >= 4 ? (LPR == 4 ? 4 : LPR == 8 ? 3 : 2) : (LPR == 16 ? 3 : 8 / RB);
   static_assert(RPW % 16 == 0, "blocks of 16 rows");
   using VecT = typename DVec<KV>::type;
 

@@ -102,7 +102,8 @@ def test_spmmv_misaligned_block():
 def test_spmmv_rows_kernel_equals_pass_kernel(k, C, sigma, seg):
     """With the automatic pass width k = 32 and 64 (and 16 on dense layouts:
     sigma = 1 leaves these padding-heavy, sigma = n dense) run the one-pass
-    kernel with 8 lanes per row; an explicit k-tile runs the pass kernel. Both add each row's products in column order: equal bit for
+    kernel with 8 lanes per row (4 for k = 16); an explicit k-tile runs the
+    pass kernel. Both add each row's products in column order: equal bit for
     bit, and within the oracle's bound (split rows included)."""
     A = synth.powerlaw(30_000, seed=51)
     X = synth.block_vector(A.ncols, k, seed=52)
