@@ -82,10 +82,10 @@ typedef struct {
                            before the chunk is split across waves (rounded up to
                            a multiple of 64): 0 auto, < 0 never split */
   int32_t ktile;        /* right-hand sides per pass in sell_spmmv: 0 auto, else a
-                           power of two <= 64. Auto with k = 32 or 64, and 16
-                           when beta >= 0.5 (C >= 16, X and Y aligned to 16
-                           bytes), runs one pass with 8 lanes per row (4 for
-                           k = 16), each reading 4 or 8 right-hand sides */
+                           power of two <= 64. Auto with k = 16, 32 or 64
+                           (C >= 16, X and Y aligned to 16 bytes) runs one
+                           pass with 8 lanes per row (4 for k = 16), each
+                           reading 4 or 8 right-hand sides */
   int32_t kmax;         /* largest k sell_spmmv will be called with on matrices
                            whose chunks are split (sizes the partial-sum buffer):
                            0 means 32 */

@@ -100,10 +100,9 @@ def test_spmmv_misaligned_block():
 @pytest.mark.parametrize("k", [16, 32, 64])
 @pytest.mark.parametrize("C,sigma,seg", [(16, 1, 64), (32, 30_000, 64), (64, 1, -1), (128, 1000, 32)])
 def test_spmmv_rows_kernel_equals_pass_kernel(k, C, sigma, seg):
-    """With the automatic pass width k = 32 and 64 (and 16 on dense layouts:
-    sigma = 1 leaves these padding-heavy, sigma = n dense) run the one-pass
-    kernel with 8 lanes per row (4 for k = 16); an explicit k-tile runs the
-    pass kernel. Both add each row's products in column order: equal bit for
+    """With the automatic pass width k = 16, 32 and 64 run the one-pass
+    kernel with 8 lanes per row (4 for k = 16), on padding-heavy (sigma = 1)
+    and dense (sigma = n) layouts; an explicit k-tile runs the pass kernel. Both add each row's products in column order: equal bit for
     bit, and within the oracle's bound (split rows included)."""
     A = synth.powerlaw(30_000, seed=51)
     X = synth.block_vector(A.ncols, k, seed=52)
