@@ -33,6 +33,7 @@ import hashlib
 import glob
 import json
 import os
+import re
 import sys
 import time
 
@@ -54,15 +55,24 @@ PAPER_CONTEXT = {
 }
 
 
+def source_hash(paths) -> str:
+    """Hash of C/C++/HIP sources without their comments and with whitespace
+    collapsed, so that an edit of a comment leaves it unchanged."""
+    h = hashlib.sha256()
+    for p in sorted(paths):
+        with open(p, encoding="utf-8") as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(os.path.basename(p).encode())
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()[:16]
+
+
 def kernel_source_hash() -> str:
     """Hash of the HIP sources: the stored counter traffic is valid only for
-    the kernels it was measured on."""
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1307_6209_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode())
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    the code it was measured on."""
+    return source_hash(glob.glob(os.path.join(ROOT, "paper_1307_6209_amd", "csrc", "*")))
 
 
 def stored_traffic(src_hash: str, split: bool = False):

@@ -639,16 +639,16 @@ sell_status spmmv_run(sell_handle h, const void *X, void *Y, int32_t k, void *st
   if (h->C < 8) return fail(SELL_ERR_UNSUPPORTED, w + ": C must be >= 8 for k > 1");
   if (!scratch && h->units && k > h->kmax) return fail(SELL_ERR_INVALID_ARG, w + ": k exceeds the kmax given at build");
   // With the automatic pass width, k = 32 and 64 run in one pass with 8
-  // lanes per row and k = 16 with 4: each row of X is read whole by two,
-  // four or eight accesses of 16 bytes per lane (X and Y aligned to 16
-  // bytes). Measured on the power-law 1M matrix at beta = 0.98 (sigma = n) /
-  // 0.14 (sigma = 1024), GF/s, with the right-hand sides as 16-byte pairs
-  // and the columns in flight of k_spmmv_rows: k = 16 4 lanes 1,124-1,132 /
-  // 420, 8 lanes 1,100 / 366 (before the pairs), pass kernel 756 / 405-407;
-  // k = 32 8 lanes 1,214 / 505,
-  // 4 lanes 1,203, 16 lanes 1,131 / 410 (before the pairs), pass kernel 862 /
-  // 402; k = 64 8 lanes 1,296 / 677, 16 lanes 1,229 / 564, pass kernel 913 /
-  // 421; k = 8 4 lanes 626, 8 lanes 457 / 191, pass kernel 686 / 293.
+  // lanes per row and k = 16 with 4: each lane reads its share of a row of X
+  // with two or four accesses of 16 bytes (X and Y aligned to 16 bytes).
+  // Measured on the power-law 1M matrix at beta = 0.98 (sigma = n) / 0.14
+  // (sigma = 1024), GF/s, with the right-hand sides as 16-byte pairs and the
+  // columns in flight of k_spmmv_rows: k = 16 4 lanes 1,124-1,132 / 420,
+  // 8 lanes 1,100 / 366 (before the pairs), pass kernel 756 / 405-407; k = 32
+  // 8 lanes 1,214 / 505, 4 lanes 1,203, 16 lanes 1,131 / 410 (before the
+  // pairs), pass kernel 862 / 402; k = 64 8 lanes 1,296 / 677, 16 lanes
+  // 1,229 / 564, pass kernel 913 / 421; k = 8 4 lanes 626, 8 lanes 457 / 191,
+  // pass kernel 686 / 293.
   {
     const int lpr = (k == 64 || k == 32) ? 8 : k == 16 ? 4 : 0;
     if (h->ktile == 0 && lpr > 0 && h->C >= 16 &&

@@ -53,3 +53,16 @@ def test_errors_against_the_oracle_on_host():
     want_c = float("%.3g" % (1e-3 / scale[5]))
     want_n = float("%.3g" % (1e-3 / np.linalg.norm(yq)))
     assert out["stencil27_160"]["bad"] == {"normwise": want_n, "componentwise": want_c}
+
+
+def test_source_hash_ignores_comments_only(tmp_path):
+    """The hash that gates the stored counter traffic changes with the code
+    and not with its comments or layout."""
+    import bench
+    a = tmp_path / "k.hip"
+    a.write_text("// kernel\n__global__ void k(int *p) { p[0] = 1; /* one */ }\n")
+    h0 = bench.source_hash([str(a)])
+    a.write_text("// the kernel, reworded\n__global__ void k(int *p) {\n  p[0] = 1;  /* the value one */\n}\n")
+    assert bench.source_hash([str(a)]) == h0
+    a.write_text("// kernel\n__global__ void k(int *p) { p[0] = 2; /* one */ }\n")
+    assert bench.source_hash([str(a)]) != h0
