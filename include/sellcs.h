@@ -281,9 +281,10 @@ sell_status sell_batch_create(const sell_handle *hs, int32_t count,
 
 /*
  * sell_batch_create_persistent -- the same batch as one persistent launch:
- * the grid is the number of wavefronts the device holds at once, and the
- * units are cut into slices of equal estimated cost (wave steps plus a fixed
- * charge per unit), one slice per wavefront, run back to back. Same
+ * the grid is the number of wavefronts the device holds at once, and each
+ * wavefront runs a list of units back to back: the units placed on an XCD
+ * are dealt, in order, to that XCD's wavefronts, each to the one with the
+ * least estimated cost so far (wave steps plus a fixed charge per unit). Same
  * arguments, ownership, errors and results as sell_batch_create; use it with
  * sell_batch_spmv and sell_batch_destroy. (One wavefront per unit, the
  * sell_batch_create form, measured faster on uneven power-law batches: the

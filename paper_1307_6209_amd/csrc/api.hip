@@ -949,7 +949,8 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
   // placement on the XCDs: each matrix (or piece of a large one) on one XCD,
   // so that its x stays in that XCD's L2 (batch_plan.h). One unit per wave
   // (filler slots where an XCD's queue is shorter), or the persistent form's
-  // equal-cost slices per resident wave.
+  // list of units per resident wave (each unit to the least-loaded wave of
+  // its XCD).
   int64_t nwaves = 0;
   if (persistent) {
     const int wpcu = std::max(1, sell::batch_waves_per_cu(B->combo, B->C, B->U));

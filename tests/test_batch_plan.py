@@ -3,7 +3,8 @@ batch_plan.h), compiled with g++ and checked on the host: every work unit
 runs exactly once; the units of a matrix (of each piece of a large one) sit
 in workgroups of one XCD (workgroup b runs on XCD b mod 8); split segments
 come before whole chunks on each XCD; the estimated cost is balanced; the
-persistent form's slices cover each XCD's queue in order."""
+persistent form deals each XCD's queue to its waves, each wave ending
+within one unit's cost of the XCD's mean."""
 import os
 import subprocess
 
@@ -115,6 +116,19 @@ def test_persistent_slices(driver, seed, nmats):
             xcd[u] = (w // W) % X
     for x in range(X):
         assert res["load"][x] == cost_a[xcd == x].sum()
+    # per XCD, the waves' estimated costs: none above the mean by more than
+    # the largest unit (list scheduling); split segments first in every wave
+    split_a = np.array(split)
+    for x in range(X):
+        waves = [w for w in range(nw) if (w // W) % X == x]
+        loads = np.array([cost_a[order[sl[w]:sl[w + 1]]].sum() for w in waves])
+        units = [u for w in waves for u in order[sl[w]:sl[w + 1]]]
+        if units:
+            assert loads.max() <= loads.mean() + cost_a[units].max()
+        for w in waves:
+            s = split_a[order[sl[w]:sl[w + 1]]]
+            if s.size and s.any() and not s.all():
+                assert np.flatnonzero(s).max() < np.flatnonzero(s == 0).min()
 
 
 def test_one_oversized_matrix_is_spread(driver):
