@@ -642,12 +642,15 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
   constexpr int G = 64 / RPW;
   constexpr int WPC = C > 64 ? C / 64 : 1;
   constexpr int KT = G * KV;
-  // chunk columns in flight: eight (four for KV = 8). Measured on the
-  // power-law 1M matrix, GF/s at sigma = n / 1024, against 8 / KV (two for
-  // KV >= 4): k = 4 337 / 186 -> 375 / 199, k = 8 462 / 256 -> 684 / 292,
-  // k = 16 (KV = 8, sigma = 1024) 386 -> 406; sixteen for KV = 1 (k = 2, 3)
-  // was 7 % slower at sigma = 1024, 32 / KV slower throughout.
-  constexpr int U = KV >= 8 ? 4 : 8;
+  // chunk columns in flight: twelve for one or two right-hand sides per
+  // lane, eight for four, four for eight. Measured on the power-law 1M
+  // matrix, GF/s at sigma = n / 1024, against 8 / KV (two for KV >= 4):
+  // k = 4 337 / 186 -> 375 / 199, k = 8 462 / 256 -> 684 / 292, k = 16
+  // (KV = 8, sigma = 1024) 386 -> 406; with the masked last round below,
+  // twelve against eight for KV <= 2: k = 2 213 -> 225, k = 4 391 -> 409
+  // (210 -> 214); sixteen 234 / 112 and 401 / 207; for KV = 4 (k = 8) four
+  // 579, six 639, eight 680.
+  constexpr int U = KV >= 8 ? 4 : KV >= 4 ? 8 : 12;
   using VecT = typename DVec<KV>::type;
 
   const int lane = threadIdx.x & 63;
@@ -708,13 +711,29 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmmv(SpmvArgs a) {
         for (int v = 0; v < KV; ++v) acc[v] = __builtin_fma(vv[u], vget<KV>(xg[u], v), acc[v]);
     }
   }
-  for (; j < je; ++j) {
-    const int32_t c = ld_col(cp + (int64_t)j * C);
-    const double vj = ld_val(vp + (int64_t)j * C);
-    if (active && vj != 0.0) {
-      const VecT xg = *reinterpret_cast<const VecT *>(X + (int64_t)c * k + v0);
+  // the last je - j < U columns as one more masked round (columns past the
+  // end read as padding), all their gathers in flight together
+  if (j < je) {
+    int32_t ci[U];
+    double vv[U];
 #pragma unroll
-      for (int v = 0; v < KV; ++v) acc[v] = __builtin_fma(vj, vget<KV>(xg, v), acc[v]);
+    for (int u = 0; u < U; ++u) {
+      ci[u] = 0;
+      vv[u] = 0.0;
+      if (j + u < je) {
+        ci[u] = ld_col(cp + (int64_t)(j + u) * C);
+        vv[u] = ld_val(vp + (int64_t)(j + u) * C);
+      }
+    }
+    if (active) {
+      VecT xg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        xg[u] = vv[u] != 0.0 ? *reinterpret_cast<const VecT *>(X + (int64_t)ci[u] * k + v0) : VecT{};
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < KV; ++v) acc[v] = __builtin_fma(vv[u], vget<KV>(xg[u], v), acc[v]);
     }
   }
 
