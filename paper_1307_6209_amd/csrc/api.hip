@@ -874,11 +874,13 @@ sell_status batch_create_impl(const sell_handle *hs, int32_t count, bool persist
   B->hs.assign(hs, hs + count);
   B->combo = h0->combo;
   B->C = h0->C;
-  // the batched kernel: one slot per lane, 4 or 8 in flight; the persistent
-  // form runs its waves' slices one unit after another and gains more from
-  // resident waves (50 instead of 70 VGPRs: eight waves per SIMD instead of
-  // seven) than from depth: 4 (64 power-law matrices at sigma = n_b: 172 -> 167 us)
-  B->U = persistent ? 4 : std::min(h0->unroll, 8);
+  // the batched kernel: one slot per lane, 4 or 8 in flight, both forms.
+  // Measured on 64 power-law matrices (sigma = n_b / 1024, us): with the
+  // persistent waves' units in consecutive equal-cost slices, 4 in flight
+  // (50 instead of 70 VGPRs: eight waves per SIMD instead of seven) gave
+  // 172 -> 167 at sigma = n_b; with each unit dealt to the least-loaded
+  // wave, 8 gives 128.0 -> 123.9 / 265.4 -> 268.3
+  B->U = std::min(h0->unroll, 8);
   B->g = sell::geom_of(h0->C, 1);  // the batched kernel loads one slot per lane
   const Geom &g = B->g;
 
