@@ -71,9 +71,9 @@ typedef struct {
   sell_dtype val_dtype; /* storage of the matrix values: F64, F32 or BF16 */
   sell_dtype acc_dtype; /* accumulation and y: F64 or F32 (F64 values need F64) */
   int32_t unroll;       /* matrix slots in flight per lane: 0 auto (16 for the x-window
-                           product with two slots per lane, else 8), or 4, 8 or 16
-                           (16 applies to the x-window product with two slots per
-                           lane; elsewhere it is taken as 8) */
+                           product with two or four slots per lane, else 8), or 4, 8
+                           or 16 (16 applies to the x-window product with two or four
+                           slots per lane; elsewhere it is taken as 8) */
   int32_t vec;          /* consecutive slots (rows) each lane loads at once: 0 auto
                            (2 for F64 values with >= 8 nonzeros per row on average,
                            and for F32/BF16 values when the x window is used; else
@@ -102,7 +102,8 @@ typedef struct {
                            streamed instead of 4, x read from LDS; same result
                            bit for bit). 0: used when it fits and the matrix has
                            at least two groups of 4 chunks per compute unit (C in
-                           8..64, vec 1 or 2, no split chunks, at most 8192
+                           8..64, vec 1 or 2 -- or 4 with FP32/BF16 values and
+                           C >= 16 -- no split chunks, at most 8192
                            slots and 1024 runs of consecutive columns per group,
                            window <= 4 KiB times G); -1: never; 1: required
                            (SELL_ERR_UNSUPPORTED when it cannot be built, window

@@ -425,14 +425,17 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
   if (o.xwindow >= 0) {
     const int V = g.V;
     const int64_t ngroups_all = (nc + sell::kXwChunks - 1) / sell::kXwChunks;
-    const bool shape_ok = C >= 8 && C <= 64 && (V == 1 || V == 2) && !h->units && h->padded > 0;
+    const bool shape_ok = C >= 8 && C <= 64 && (V == 1 || V == 2 || (V == 4 && C >= 16 && h->vdt != SELL_F64)) &&
+                          !h->units && h->padded > 0;
     // automatic mode skips small matrices: with fewer than two workgroups per
     // CU the product is latency-bound and the staging round trip only adds
     // to it (the 128^2 Laplacian: 2.4 us per call without, 3.1 with)
     const bool big_enough = o.xwindow == 1 || ngroups_all >= 2 * (int64_t)di.cus;
     if (!shape_ok || !big_enough) {
       if (o.xwindow == 1)
-        return fail(SELL_ERR_UNSUPPORTED, "sell_build: the x window needs C in 8..64, vec 1 or 2 and no split chunks");
+        return fail(SELL_ERR_UNSUPPORTED,
+                    "sell_build: the x window needs C in 8..64, vec 1 or 2 (or 4 with FP32/BF16 values and C >= 16) "
+                    "and no split chunks");
     } else {
       // at C = 32, groups of kXwChunksWide chunks when their windows fit
       // (fewer workgroups stage the x lines that neighbouring chunks share;
@@ -507,7 +510,7 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
         // with two slots per lane the window kernel keeps eight wave steps
         // in flight by default (measured on the 27-point stencil at C = 32:
         // FP64 1,186 -> 1,228 GF/s, BF16 2,170 -> 2,389; neutral at C = 64)
-        if (h->g.V == 2 && (o.unroll == 0 || o.unroll == 16)) h->unroll = 16;
+        if (h->g.V >= 2 && (o.unroll == 0 || o.unroll == 16)) h->unroll = 16;
       }
     }
   }
@@ -1219,8 +1222,8 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
       }
       for (int iu = 0; iu < nU; ++iu) {
         if (Us[iu] != 4 && Us[iu] != 8 && Us[iu] != 16) continue;
-        // sixteen slots in flight: only the window kernel with two per lane
-        if (Us[iu] == 16 && !(h->lcol && h->g.V == 2)) continue;
+        // sixteen slots in flight: only the window kernel with two or four per lane
+        if (Us[iu] == 16 && !(h->lcol && h->g.V >= 2)) continue;
         for (int ik = 0; ik < (k > 1 ? nK : 1); ++ik) {
           h->unroll = std::max(Us[iu], h->g.V);
           h->ktile = k > 1 ? Ks[ik] : 0;

@@ -1025,8 +1025,9 @@ hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a
   return skip_zero ? launch_spmv_zs<COMBO, true>(C, U, VV, a, s) : launch_spmv_zs<COMBO, false>(C, U, VV, a, s);
 }
 
-// C in {8, 16, 32, 64}; U * V slots in flight per lane: 4 or 8; w.gc chunks
-// per workgroup: kXwChunks or kXwChunksWide.
+// C in {8, 16, 32, 64}; V slots per lane (1, 2, or 4 for FP32/BF16 values,
+// C >= 16), U wave steps in flight (U * V = 4, 8 or 16); w.gc chunks per
+// workgroup: kXwChunks or kXwChunksWide.
 template <int COMBO, int GC>
 hipError_t launch_spmv_xw_g(int C, int VV, int U, const SpmvArgs &a, const XwArgs &w, size_t lds, hipStream_t s) {
   const unsigned nb = (unsigned)((a.nwork + GC - 1) / GC);
@@ -1040,6 +1041,12 @@ hipError_t launch_spmv_xw_g(int C, int VV, int U, const SpmvArgs &a, const XwArg
   SELL_L(8, 2, 2) SELL_L(16, 2, 2) SELL_L(32, 2, 2) SELL_L(64, 2, 2)
   SELL_L(8, 2, 4) SELL_L(16, 2, 4) SELL_L(32, 2, 4) SELL_L(64, 2, 4)
   SELL_L(8, 2, 8) SELL_L(16, 2, 8) SELL_L(32, 2, 8) SELL_L(64, 2, 8)
+  // four slots per lane: FP32/BF16 values (16 or 8 bytes per load)
+  if constexpr (sizeof(typename Types<COMBO>::V) <= 4) {
+    SELL_L(16, 4, 1) SELL_L(32, 4, 1) SELL_L(64, 4, 1)
+    SELL_L(16, 4, 2) SELL_L(32, 4, 2) SELL_L(64, 4, 2)
+    SELL_L(16, 4, 4) SELL_L(32, 4, 4) SELL_L(64, 4, 4)
+  }
 #undef SELL_L
   return hipErrorInvalidValue;
 }

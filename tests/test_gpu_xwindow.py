@@ -92,7 +92,7 @@ def test_window_equals_global_index_product(name, make, C, sigma, vec, gc):
 
 @pytest.mark.parametrize("val_dtype,acc", [("f32", "f32"), ("f32", "f64"), ("bf16", "f32"), ("bf16", "f64")])
 @pytest.mark.parametrize("C", [32, 64])
-@pytest.mark.parametrize("vec", [1, 2])
+@pytest.mark.parametrize("vec", [1, 2, 4])
 def test_window_reduced_precision_bitwise(val_dtype, acc, C, vec):
     A = synth.stencil27(20)
     x = oracle.round_f32(synth.uniform(A.ncols, 32, 1)).astype(np.float64)
