@@ -401,6 +401,17 @@ def run_forms(args, probes, checks, checks_x) -> dict:
         hist[key] = hist.get(key, 0) + 1
     out["batch64_autotuned"] = {"C": tb["C"], "gfs": round(tb["gflops"], 2), "us": round(tb["us_per_call"], 2),
                                 "sigma_counts": hist, "candidates": tb["candidates"]}
+    # the autotuned batch in both launch forms, vectors marshalled once
+    hs = [sellcs.sell_build(rr, cc, vv, B.ncols, tb["C"], sg) for ((rr, cc, vv), B), sg in
+          zip(zip(devs, mats), tb["sigmas"])]
+    for key, form in (("us_timed", sellcs.sell_batch_create), ("persistent_us", sellcs.sell_batch_create_persistent)):
+        bb = form(hs)
+        bbv = sellcs.BatchVectors(bb, xs, ys)
+        t = time_calls(lambda: sellcs.sell_batch_spmv(bb, bbv), max(10, args.steps // 10), 3)
+        out["batch64_autotuned"][key] = round(t * 1e6, 2)
+        bb.close()
+    for hh in hs:
+        hh.close()
     del devs
     # power-law n = 2,000,000: plain and globally sorted
     progress("power-law 2M")

@@ -158,8 +158,9 @@ def test_spmmv_powerlaw_1m_sigma_n(powerlaw_1m):
     h.close()
 
 
-# the block form's autotuned winner at k = 32: C = 16, sigma = n, 16
-# right-hand sides per pass
+# the pass kernel's best shape at k = 32 (C = 16, sigma = n, 16 right-hand
+# sides per pass; the autotuner's winner before the one-pass kernel took
+# k = 32)
 def test_spmmv_powerlaw_1m_tuned_k32(powerlaw_1m):
     A = powerlaw_1m
     h = build(A, 16, A.nrows, kmax=32, ktile=16)
@@ -167,15 +168,18 @@ def test_spmmv_powerlaw_1m_tuned_k32(powerlaw_1m):
     h.close()
 
 
+@pytest.mark.parametrize("C", [16, 32])
 @pytest.mark.parametrize("form", ["sell_batch_create", "sell_batch_create_persistent"])
 @pytest.mark.parametrize("sigma", ["mixed", "n"])
-def test_batch_64(form, sigma):
+def test_batch_64(form, sigma, C):
+    """The 64-matrix batch in both launch forms, at C = 32 and at the batch
+    autotuner's choice on this workload, C = 16."""
     import torch
     from paper_1307_6209_amd import sellcs
     mats = synth.batch_workload(64)
-    say("batch", form, "sigma", sigma, "rows", sum(A.nrows for A in mats), "nnz", sum(A.nnz for A in mats))
+    say("batch", form, "C", C, "sigma", sigma, "rows", sum(A.nrows for A in mats), "nnz", sum(A.nnz for A in mats))
     sig = [1, 32, 1024, 16384]
-    hs = [build(A, 32, sig[i % 4] if sigma == "mixed" else A.nrows) for i, A in enumerate(mats)]
+    hs = [build(A, C, sig[i % 4] if sigma == "mixed" else A.nrows) for i, A in enumerate(mats)]
     b = getattr(sellcs, form)(hs)
     xs = [synth.uniform(A.ncols, synth.SEED_X + 10 + i) for i, A in enumerate(mats)]
     xd = [torch.from_numpy(x).cuda() for x in xs]
@@ -183,5 +187,5 @@ def test_batch_64(form, sigma):
     sellcs.sell_batch_spmv(b, xd, yd)
     torch.cuda.synchronize()
     for A, h, x, y in zip(mats, hs, xs, yd):
-        check_fp64(A, y.cpu().numpy(), x, m=batch_chain_per_row(A, h, 32))
+        check_fp64(A, y.cpu().numpy(), x, m=batch_chain_per_row(A, h, C))
     b.close()
