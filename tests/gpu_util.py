@@ -5,7 +5,6 @@ import sys
 import numpy as np
 
 import oracle
-import synth
 
 U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
 

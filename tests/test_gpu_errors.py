@@ -1,6 +1,5 @@
 """Error behaviour of the library on the device (malformed CRS detected by
 the validation kernels, bad dtype/size combinations)."""
-import numpy as np
 import pytest
 
 import synth

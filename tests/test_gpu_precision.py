@@ -1,7 +1,6 @@
 """Reduced-precision forms: values stored in FP32 or BF16 (rounded to nearest
 even from FP64 at build), x in FP32, accumulation in FP32 or FP64, with
 componentwise error bounds against the oracle."""
-import numpy as np
 import pytest
 
 import synth

@@ -8,7 +8,6 @@ the cross-lane sum and the segments of a split row), capped at
 import numpy as np
 import pytest
 
-import oracle
 import synth
 from gpu_util import build, chain_per_row, check_fp64, check_reduced, say, spmv_gpu
 
