@@ -66,3 +66,17 @@ def test_source_hash_ignores_comments_only(tmp_path):
     assert bench.source_hash([str(a)]) == h0
     a.write_text("// kernel\n__global__ void k(int *p) { p[0] = 2; /* one */ }\n")
     assert bench.source_hash([str(a)]) != h0
+
+
+def test_read_write_bound_arithmetic():
+    """The read/write bound of the benchmark line: reads at the read probe's
+    rate, then writes at the write probe's rate, against the measured time;
+    with counters, the same for the counted bytes."""
+    import bench
+    probes = {"read_gbs": 8000.0, "write_gbs": 4000.0}
+    r = bench.read_write_bound(8e9, 4e9, probes, 2.5e-3)  # 1 ms of reads, 1 ms of writes
+    assert r["us"] == 2000.0 and r["frac"] == 0.8
+    r = bench.read_write_bound(8e9, 4e9, probes, 2.5e-3, traffic=(16e9, 0.0))
+    assert "counted_frac" not in r  # a zero write count is no measurement
+    r = bench.read_write_bound(8e9, 4e9, probes, 2.5e-3, traffic=(16e9, 4e9))
+    assert r["counted_us"] == 3000.0 and r["counted_frac"] == 1.2
