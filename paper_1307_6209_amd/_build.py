@@ -29,9 +29,30 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+# spmv_combo.hip holds the launchers of one dtype combination (values, x,
+# accumulation); it is compiled once per entry, as (launcher suffix, enumerator).
+COMBO_SRC = "spmv_combo.hip"
+COMBOS = [("f64_f64", "COMBO_F64_F64"), ("f32_f32", "COMBO_F32_F32"), ("f32_f64", "COMBO_F32_F64"),
+          ("bf16_f32", "COMBO_BF16_F32"), ("bf16_f64", "COMBO_BF16_F64")]
+
+
+def units(csrc: str = CSRC):
+    """The compile units: (source, extra flags, object file name)."""
+    out = []
+    for src in sorted(glob.glob(os.path.join(csrc, "*.hip"))):
+        name = os.path.basename(src)
+        if name == COMBO_SRC:
+            for lc, combo in COMBOS:
+                out.append((src, ["-DSELL_COMBO=" + combo, "-DSELL_LC=" + lc], "spmv_%s.o" % lc))
+        else:
+            out.append((src, [], name + ".o"))
+    return out
+
+
+def _compile(unit) -> str:
+    src, defs, name = unit
+    obj = os.path.join(OBJ, name)
+    cmd = [HIPCC, *CFLAGS, *defs, "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (p.stdout + p.stderr).splitlines() if "packed-fp32-ops" not in l)
     if p.returncode != 0:
@@ -43,10 +64,10 @@ def _compile(src: str) -> str:
 
 def build(jobs: int | None = None) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    todo = units()
+    jobs = jobs or min(len(todo), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(_compile, todo))
     tmp = LIB + ".tmp%d" % os.getpid()
     p = subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp],
                        capture_output=True, text=True)
