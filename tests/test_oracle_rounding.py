@@ -32,7 +32,8 @@ def test_bf16_matches_torch_on_binary32_inputs():
     """For values already exactly binary32, rounding to bfloat16 must agree
     with torch's float32 -> bfloat16 conversion (nearest-even)."""
     torch = pytest.importorskip("torch")
-    f = _interesting_doubles(200_000, 3).astype(np.float32)
+    with np.errstate(over="ignore"):  # values past the binary32 range become inf and are dropped
+        f = _interesting_doubles(200_000, 3).astype(np.float32)
     f = f[np.isfinite(f)]
     want = torch.from_numpy(f).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     got = oracle.round_bf16(f.astype(np.float64))
