@@ -113,6 +113,20 @@ struct Temp {
   }
 };
 
+// Two timing events, destroyed at scope exit (also when creating the second
+// one failed).
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t create() {
+    const hipError_t e = hipEventCreate(&a);
+    return e != hipSuccess ? e : hipEventCreate(&b);
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 void *owned_alloc(sell_matrix *h, const Mem &mem, size_t bytes) {
   Mem m = mem;
   void *p = m.get(bytes);
@@ -1155,16 +1169,9 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   void *y = tmp.get(ys * (size_t)std::max<int64_t>(1, A->nrows) * (size_t)k);
   if (!x || !y) return fail(SELL_ERR_OOM, "sell_autotune: vectors");
   SELL_HIP(hipMemsetAsync(x, 0, xs * (size_t)std::max<int64_t>(1, A->ncols) * (size_t)k, s));
-  hipEvent_t e0, e1;
-  SELL_HIP(hipEventCreate(&e0));
-  SELL_HIP(hipEventCreate(&e1));
-  struct Ev {
-    hipEvent_t a, b;
-    ~Ev() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-    }
-  } ev{e0, e1};
+  EventPair ev;
+  SELL_HIP(ev.create());
+  hipEvent_t e0 = ev.a, e1 = ev.b;
 
   // Model-guided search: rank every (C, sigma) by the bytes the code-balance
   // model assigns one product (padded matrix, x once, y, permutation, chunk
@@ -1268,9 +1275,6 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   return SELL_OK;
 }
 
-// ===========================================================================
-// Bandwidth probes
-// ===========================================================================
 extern "C" sell_status sell_batch_autotune(const sell_crs *As, int32_t count, const sell_tune_space *space,
                                            void *stream, sell_batch_tuned *best, int64_t *sigma_out) {
   if (!As || count < 1 || !best || !sigma_out) return fail(SELL_ERR_INVALID_ARG, "sell_batch_autotune: bad arguments");
@@ -1313,16 +1317,9 @@ extern "C" sell_status sell_batch_autotune(const sell_crs *As, int32_t count, co
     xp[b] = x + xs * xoff[b];
     yp[b] = y + ys * yoff[b];
   }
-  hipEvent_t e0, e1;
-  SELL_HIP(hipEventCreate(&e0));
-  SELL_HIP(hipEventCreate(&e1));
-  struct Ev {
-    hipEvent_t a, b;
-    ~Ev() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-    }
-  } ev{e0, e1};
+  EventPair ev;
+  SELL_HIP(ev.create());
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   // handles and batch of one candidate, released on every exit
   struct Trial {
     std::vector<sell_handle> hs;
@@ -1392,6 +1389,9 @@ extern "C" sell_status sell_batch_autotune(const sell_crs *As, int32_t count, co
   return SELL_OK;
 }
 
+// ===========================================================================
+// Bandwidth probes
+// ===========================================================================
 extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t reps, void *stream, double *gbs) {
   if (!gbs || reps < 1 || kind < 0 || kind > 9 || bytes < (1u << 20))
     return fail(SELL_ERR_INVALID_ARG, "sell_probe_bandwidth: bad arguments");
@@ -1424,9 +1424,9 @@ extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t 
     return e;
   };
   SELL_HIP(run());
-  hipEvent_t e0, e1;
-  SELL_HIP(hipEventCreate(&e0));
-  SELL_HIP(hipEventCreate(&e1));
+  EventPair ev;
+  SELL_HIP(ev.create());
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   double total_ms = 0.0;
   hipError_t err = hipSuccess;
   for (int r = 0; r < reps && err == hipSuccess; ++r) {
@@ -1438,8 +1438,6 @@ extern "C" sell_status sell_probe_bandwidth(int32_t kind, size_t bytes, int32_t 
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
     total_ms += ms;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail("sell_probe_bandwidth", err);
   *gbs = (double)moved * reps / (total_ms * 1e-3) * 1e-9;
   return SELL_OK;
