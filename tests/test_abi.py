@@ -134,3 +134,28 @@ def test_library_binds_to_torchs_hip_runtime():
     import json
     rts = json.loads(out.stdout.strip().splitlines()[-1])
     assert len(rts) == 1, rts
+
+
+def test_every_dtype_combination_is_compiled(L):
+    """The build compiles the instantiation source once per DtypeCombo
+    enumerator, under the launcher suffixes dispatch.hip declares, and the
+    library defines every combination's launchers (a missing one would only
+    show as an unresolved symbol at its first call)."""
+    import shutil
+    import subprocess
+    from paper_1307_6209_amd import _build, sellcs
+    csrc = os.path.join(ROOT, "paper_1307_6209_amd", "csrc")
+    enum = re.search(r"enum DtypeCombo \{(.*?)\};", open(os.path.join(csrc, "sell_internal.h")).read(), re.S).group(1)
+    combos = re.findall(r"(COMBO_\w+)\s*=", enum)
+    declared = re.findall(r"^SELL_DECL\((\w+)\)", open(os.path.join(csrc, "dispatch.hip")).read(), re.M)
+    built = [dict(d[2:].split("=") for d in defs) for src, defs, _ in _build.units()
+             if os.path.basename(src) == _build.COMBO_SRC]
+    assert sorted(b["SELL_COMBO"] for b in built) == sorted(combos)
+    assert sorted(b["SELL_LC"] for b in built) == sorted(declared)
+    if shutil.which("nm") is None:
+        pytest.skip("nm is not available")
+    syms = subprocess.run(["nm", "-C", "--defined-only", sellcs.LIB_PATH], capture_output=True, text=True,
+                          check=True).stdout
+    for lc in declared:
+        for fn in ("launch_spmv_", "launch_spmv_xw_", "launch_batch_", "batch_waves_per_cu_"):
+            assert "sell::%s%s(" % (fn, lc) in syms, fn + lc
