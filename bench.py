@@ -441,6 +441,14 @@ def run_forms(args, probes, checks, checks_x) -> dict:
             grid["C%d_sigma%d" % (C, s)] = {"beta": round(h.info["beta"], 4), "gfs": round(2.0 * A.nnz / t * 1e-9, 2)}
             h.close()
     pl["c_sigma_grid"] = grid
+    # lanes stopped at their rows' ends (row lengths kept, the GPU form of the
+    # kernel of Sect. 3.4): the loads of padding are skipped, the idle lanes
+    # of a chunk's short rows remain
+    for s in (1, 2**10, 2**14, A.nrows):
+        h = sellcs.sell_build(r, c, v, A.ncols, 32, s, row_lengths=True)
+        t = time_calls(lambda: sellcs.sell_spmv(h, x, y), max(20, args.steps // 5), 5)
+        pl["C32_sigma%d_row_lengths" % s] = {"gfs": round(2.0 * A.nnz / t * 1e-9, 2), "beta": round(h.info["beta"], 4)}
+        h.close()
     # reduced-precision storage at the globally sorted layout (int32 column
     # indices: the uniform half of the columns leaves no x window); the
     # results go to the oracle leg for their errors

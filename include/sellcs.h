@@ -113,6 +113,20 @@ typedef struct {
   int32_t xwindow_chunks; /* G, chunks per x-window group: 0 auto (8 at C = 32
                            when those windows fit and leave two groups per
                            compute unit, else 4), or 4 or 8 (that size only) */
+  int32_t row_lengths;  /* 1: also keep the length of every row in sorted order
+                           (4 bytes per row of the padded chunks), and sell_spmv
+                           runs each row's lanes only to the row's own length --
+                           the GPU form of the kernel that Sect. 3.4 describes:
+                           the value and index loads of padding are skipped
+                           (the plain kernel skips only their x gathers); same
+                           result bit for bit (the padding still multiplies
+                           zero by zero). The lanes of a short row still wait
+                           for the chunk's longest one, so the gain is small:
+                           a few per cent on low-beta layouts, none near
+                           beta = 1. Needs C in 8..64 (SELL_ERR_UNSUPPORTED
+                           otherwise). Used by the global-index sell_spmv only:
+                           not by the x-window product (a layout with a window
+                           runs that), sell_spmmv or the batch. 0: off. */
 } sell_build_opts;
 
 typedef struct {
@@ -138,6 +152,7 @@ typedef struct {
   int32_t xwindow_max;   /* largest window, in x elements */
   int64_t xsegments;     /* runs of consecutive columns over all windows */
   int32_t xwindow_group_chunks; /* chunks that share one x window (a workgroup): 4 or 8; 0 without window */
+  int32_t row_lengths;   /* 1 when built with row_lengths */
 } sell_info_t;
 
 /*

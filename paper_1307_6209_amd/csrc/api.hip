@@ -241,6 +241,8 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
   if (o.xwindow < -1 || o.xwindow > 1) return fail(SELL_ERR_INVALID_ARG, "sell_build: xwindow must be -1, 0 or 1");
   if (o.xwindow_chunks != 0 && o.xwindow_chunks != sell::kXwChunks && o.xwindow_chunks != sell::kXwChunksWide)
     return fail(SELL_ERR_INVALID_ARG, "sell_build: xwindow_chunks must be 0, 4 or 8");
+  if (o.row_lengths != 0 && o.row_lengths != 1) return fail(SELL_ERR_INVALID_ARG, "sell_build: row_lengths must be 0 or 1");
+  if (o.row_lengths && (C < 8 || C > 64)) return fail(SELL_ERR_UNSUPPORTED, "sell_build: row_lengths needs C in 8..64");
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::unique_ptr<sell_matrix> h(new sell_matrix());
@@ -358,6 +360,13 @@ sell_status build_impl(const sell_crs *A, int32_t C, int64_t sigma, const sell_b
     }
     SELL_HIP(sell::build_fill(A->rpt, A->col, A->val, n, C, h->perm, len, h->cs, nc, h->padded, iperm, h->col,
                               h->val, (int)h->vdt, s));
+  }
+  // length of every row in sorted order, for the product whose lanes stop at
+  // their rows' ends
+  if (o.row_lengths) {
+    h->rl = static_cast<int32_t *>(owned_alloc(h.get(), mem, sizeof(int32_t) * (size_t)std::max<int64_t>(nc * C, 1)));
+    if (!h->rl) return fail(SELL_ERR_OOM, "sell_build: row lengths");
+    SELL_HIP(sell::build_sorted_len(len, h->perm, n, nc * C, h->rl, s));
   }
 
   // host copy of the chunk widths, then the work plan
@@ -579,6 +588,7 @@ sell_status spmv_run(sell_handle h, const void *x, void *y, void *stream, void *
   if (h->nrows == 0) return SELL_OK;
   sell::SpmvArgs a = args_of(h, x, y);
   if (partial) a.partial = partial;
+  a.rl = h->rl;  // row_lengths: each row's lanes stop at its end
   if (h->units1) {  // whole chunks of width 0 or 1 grouped 64 / C per wave
     a.units = h->units1;
     a.nwork = h->nunits1;
@@ -783,6 +793,7 @@ extern "C" sell_status sell_info(sell_handle h, sell_info_t *info) {
   r.xwindow_max = h->xwin_max;
   r.xsegments = h->nxseg;
   r.xwindow_group_chunks = h->lcol ? h->xw_gc : 0;
+  r.row_lengths = h->rl ? 1 : 0;
   *info = r;
   return SELL_OK;
 }

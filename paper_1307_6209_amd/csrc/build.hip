@@ -359,6 +359,15 @@ __global__ void __launch_bounds__(kBlock) k_invert(const int32_t *__restrict__ p
   if (p < n) iperm[perm[p]] = (int32_t)p;
 }
 
+// rl[p] = len[perm[p]]: the length of the row in sorted position p, 0 for
+// the rows that pad the last chunk (p in [n, np))
+__global__ void __launch_bounds__(kBlock) k_sorted_len(const int32_t *__restrict__ len,
+                                                       const int32_t *__restrict__ perm, int64_t n, int64_t np,
+                                                       int32_t *__restrict__ rl) {
+  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p < np) rl[p] = p < n ? len[perm ? (int64_t)perm[p] : p] : 0;
+}
+
 // out[p] = in[perm[p]] (gather into sorted order) or out[perm[p]] = in[p]
 // (scatter back), for elements of ES bytes.
 template <typename E, bool SCATTER>
@@ -374,6 +383,13 @@ __global__ void __launch_bounds__(kBlock) k_permute(const E *__restrict__ in, E 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+hipError_t build_sorted_len(const int32_t *len, const int32_t *perm, int64_t n, int64_t np, int32_t *rl,
+                            hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sorted_len, dim3(blocks_for(np, kBlock)), dim3(kBlock), 0, s, len, perm, n, np, rl);
+  return hipGetLastError();
+}
 
 hipError_t build_invert(const int32_t *perm, int64_t n, int32_t *iperm, hipStream_t s) {
   if (n <= 0) return hipSuccess;

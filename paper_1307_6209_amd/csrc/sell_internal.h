@@ -95,6 +95,8 @@ struct SpmvArgs {
   int64_t nsplit;
   void *partial;
   int32_t seg_cols;     // chunk columns per segment (multiple of kSegAlign)
+  const int32_t *rl;    // single-vector product: length of every row in sorted
+                        // order (N_c * C entries), or nullptr
   // block form only
   int32_t k;            // right-hand sides
   int32_t kt;           // right-hand sides per pass (ktile)
@@ -193,6 +195,9 @@ hipError_t build_fill(const int64_t *rpt, const int32_t *col, const double *val,
                       int64_t padded, const int32_t *cmap, int32_t *scol, void *sval, int val_dtype,
                       hipStream_t s);
 hipError_t build_invert(const int32_t *perm, int64_t n, int32_t *iperm, hipStream_t s);
+// rl[p] = length of the row in sorted position p (0 for p >= n), p < np
+hipError_t build_sorted_len(const int32_t *len, const int32_t *perm, int64_t n, int64_t np, int32_t *rl,
+                            hipStream_t s);
 // x windows of groups of gc consecutive chunks: segment count per group
 // (nseg: ngroups + 1 int64, the last set to 0), the largest window (*maxwin,
 // zeroed by the caller), flag bit 1 when a group holds more than kXwMaxSlots
@@ -244,6 +249,7 @@ struct sell_matrix {
   int device = 0;
 
   int32_t *perm = nullptr;
+  int32_t *rl = nullptr;   // row_lengths: length of every row in sorted order (N_c * C)
   int32_t *cl = nullptr;
   int64_t *cs = nullptr;
   int32_t *col = nullptr;

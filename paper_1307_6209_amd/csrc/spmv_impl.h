@@ -108,9 +108,12 @@ __device__ __forceinline__ float fmac(float v, float x, float acc) { return __bu
 // the word inside it and wait for each load before issuing the next. Values
 // narrower than 32 bits are returned widened (R), so that the compiler does
 // not pack the values of several steps into shared registers either.
+//
+// lim (<= cl) limits the loads only: a lane whose step lies at or past lim
+// loads slot 0 instead (the caller then zeroes what it loaded).
 template <int U, int VV, typename I, typename V, typename R>
 __device__ __forceinline__ void ld_batch(const I *ci_base, const V *v_base, int64_t off0, int64_t stride, int s0,
-                                         int se, int T, int t, int cl, bool (&ok)[U], I (&ci)[U][VV],
+                                         int se, int T, int t, int cl, int lim, bool (&ok)[U], I (&ci)[U][VV],
                                          R (&raw)[U][VV]) {
   constexpr bool kSkip = VV == 1 || (sizeof(I) >= 4 && sizeof(V) >= 4);
 #pragma unroll
@@ -118,7 +121,7 @@ __device__ __forceinline__ void ld_batch(const I *ci_base, const V *v_base, int6
     const int ss = s0 + u;
     ok[u] = ss < se && ss * T + t < cl;
     if (!kSkip || ss < se) {
-      const int64_t o = ok[u] ? off0 + (int64_t)ss * stride : 0;
+      const int64_t o = ok[u] && ss * T + t < lim ? off0 + (int64_t)ss * stride : 0;
       ld_stream<VV>(ci_base + o, ci[u]);
       V r[VV];
       ld_stream<VV>(v_base + o, r);
@@ -144,15 +147,22 @@ __device__ __forceinline__ void opaque(T &v) {
 // Lane l holds the VV consecutive slots VV*l .. VV*l+VV-1 of every wave step
 // (64*VV consecutive slots = T chunk columns of RPW rows): rows
 // rl0 .. rl0+VV-1 with rl0 = (VV*l) % RPW, column offset t = (VV*l) / RPW.
-// With ZS, slots holding value 0 (padding) skip the gather; that pays on
-// padding-heavy layouts and costs a compare per slot on dense ones.
-template <int COMBO, int C, int U, int VV, bool ZS>
+// With ZS (1 or 2), slots holding value 0 (padding) skip the gather; that
+// pays on padding-heavy layouts and costs a compare per slot on dense ones.
+// With ZS == 2 the lane also holds the lengths of its rows (rlp, in sorted
+// order) and loads nothing past them -- the GPU form of the kernel in which
+// each row's lane runs only to the row's own length (Sect. 3.4): a step past
+// all of a lane's rows loads slot 0 (one line every lane shares) and the
+// slots past a row's end are zeroed, so the arithmetic -- padding multiplies
+// zero by zero -- and the result are those of the plain product.
+template <int COMBO, int C, int U, int VV, int ZS>
 __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const int32_t *__restrict__ col,
                                           const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
                                           const int32_t *__restrict__ perm, const void *__restrict__ xv,
                                           void *__restrict__ yv, int64_t nrows, int32_t item, int32_t seg,
                                           int32_t nseg, int64_t poff, void *__restrict__ partial,
-                                          int32_t seg_cols, int lane) {
+                                          int32_t seg_cols, int lane, const int32_t *__restrict__ rlp = nullptr) {
+  constexpr bool RL = ZS == 2;
   using V = typename Types<COMBO>::V;
   using X = typename Types<COMBO>::X;
   using A = typename Types<COMBO>::A;
@@ -180,6 +190,17 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
   const int32_t *cp = col + off0;
   const V *vp = static_cast<const V *>(valv) + off0;
   const X *x = static_cast<const X *>(xv);
+  // ZS == 2: the lengths of the lane's rows and the longest of them
+  int rlen[VV];
+  int lmax = je;
+  if constexpr (RL) {
+    lmax = 0;
+#pragma unroll
+    for (int v = 0; v < VV; ++v) {
+      rlen[v] = rlp[chunk * C + h * RPW + rl0 + v];
+      lmax = rlen[v] > lmax ? rlen[v] : lmax;
+    }
+  }
 
   A acc[VV];
 #pragma unroll
@@ -190,8 +211,24 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
     V raw[U][VV];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
-      ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
+      if constexpr (RL) {
+        const bool live = (s + u) * T + t < lmax;
+        ld_stream<VV>(live ? cp + (int64_t)(s + u) * STRIDE : col, ci[u]);
+        ld_stream<VV>(live ? vp + (int64_t)(s + u) * STRIDE : static_cast<const V *>(valv), raw[u]);
+      } else {
+        ld_stream<VV>(cp + (int64_t)(s + u) * STRIDE, ci[u]);
+        ld_stream<VV>(vp + (int64_t)(s + u) * STRIDE, raw[u]);
+      }
+    }
+    if constexpr (RL) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < VV; ++v)
+          if ((s + u) * T + t >= rlen[v]) {
+            raw[u][v] = 0;
+            ci[u][v] = 0;
+          }
     }
     X xg[U][VV];
 #pragma unroll
@@ -209,7 +246,17 @@ __device__ __forceinline__ void spmv_unit(const void *__restrict__ valv, const i
     using R = typename std::conditional<sizeof(V) < 4 && VV == 1, uint32_t, V>::type;
     R raw[U][VV];
     bool ok[U];
-    ld_batch<U, VV>(col, static_cast<const V *>(valv), off0, STRIDE, s, se, T, t, je, ok, ci, raw);
+    ld_batch<U, VV>(col, static_cast<const V *>(valv), off0, STRIDE, s, se, T, t, je, lmax, ok, ci, raw);
+    if constexpr (RL) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < VV; ++v)
+          if ((s + u) * T + t >= rlen[v]) {
+            raw[u][v] = 0;
+            ci[u][v] = 0;
+          }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -503,11 +550,12 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_combine(SpmvArgs a) {
 // (a butterfly over lane offsets 32, 16, ..., C with the missing columns as
 // +0), so the result is the same bit for bit; slots holding 0 skip the
 // gather.
-template <int COMBO, int C>
+template <int COMBO, int C, bool RL = false>
 __device__ __forceinline__ void spmv_group(const void *__restrict__ valv, const int32_t *__restrict__ col,
                                            const int64_t *__restrict__ cs, const int32_t *__restrict__ clp,
                                            const int32_t *__restrict__ perm, const void *__restrict__ xv,
-                                           void *__restrict__ yv, int64_t nrows, int32_t item, int lane) {
+                                           void *__restrict__ yv, int64_t nrows, int32_t item, int lane,
+                                           const int32_t *__restrict__ rlp = nullptr) {
   using V = typename Types<COMBO>::V;
   using X = typename Types<COMBO>::X;
   using A = typename Types<COMBO>::A;
@@ -516,7 +564,8 @@ __device__ __forceinline__ void spmv_group(const void *__restrict__ valv, const 
   const int32_t c = item + lane / C;
   const int r = lane % C;
   const int64_t p = (int64_t)c * C + r;
-  const int w = clp[c];
+  // RL: only the row's own slots are loaded (the rest stay zero, as padding)
+  const int w = RL ? rlp[p] : clp[c];
   const int64_t base = cs[c] + r;
   V v[T];
   int32_t ci[T];
@@ -539,7 +588,7 @@ __device__ __forceinline__ void spmv_group(const void *__restrict__ valv, const 
   if (p < nrows) __builtin_nontemporal_store(s[0], static_cast<A *>(yv) + (perm ? (int64_t)perm[p] : p));
 }
 
-template <int COMBO, int C, int U, int VV, bool ZS>
+template <int COMBO, int C, int U, int VV, int ZS>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -554,7 +603,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
     if (nseg > 1) poff = a.splits[u.sid].poff;
     if constexpr (C >= 8 && C <= 32) {
       if (nseg == 0) {  // a group of short chunks
-        spmv_group<COMBO, C>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, lane);
+        spmv_group<COMBO, C, ZS == 2>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, lane, a.rl);
         return;
       }
     }
@@ -562,7 +611,7 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock) k_spmv(SpmvArgs a) {
     item = (int32_t)w;
   }
   spmv_unit<COMBO, C, U, VV, ZS>(a.val, a.col, a.cs, a.cl, a.perm, a.x, a.y, a.nrows, item, seg, nseg, poff,
-                                 a.partial, a.seg_cols, lane);
+                                 a.partial, a.seg_cols, lane, a.rl);
 }
 
 // Batched form: one launch over the concatenated work units of all
@@ -1002,7 +1051,15 @@ namespace dev {
   X(1, 4) X(1, 8) X(2, 4) X(2, 8) X(4, 4) X(4, 8) X(8, 4) X(8, 8) X(16, 4) X(16, 8) X(32, 4) X(32, 8) X(64, 4) \
       X(64, 8) X(128, 4) X(128, 8)
 
-template <int COMBO, bool ZS>
+// ZS: 0 plain, 1 zero slots skip their gather, 2 also the row lengths
+// (SpmvArgs::rl); mode 2 exists for C in 8..64 and the default pairs of
+// steps in flight and slots per lane only.
+#define SELL_FOR_EACH_CUV_RL(X)                                                                               \
+  X(8, 4, 1) X(8, 8, 1) X(16, 4, 1) X(16, 8, 1) X(32, 4, 1) X(32, 8, 1) X(64, 4, 1) X(64, 8, 1) X(8, 2, 2)   \
+      X(8, 4, 2) X(16, 2, 2) X(16, 4, 2) X(32, 2, 2) X(32, 4, 2) X(64, 2, 2) X(64, 4, 2) X(8, 1, 4)           \
+          X(8, 2, 4) X(16, 1, 4) X(16, 2, 4) X(32, 1, 4) X(32, 2, 4) X(64, 1, 4) X(64, 2, 4)
+
+template <int COMBO, int ZS>
 hipError_t launch_spmv_zs(int C, int U, int VV, const SpmvArgs &a, hipStream_t s) {
   if (a.nwork <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((a.nwork + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -1015,14 +1072,19 @@ hipError_t launch_spmv_zs(int C, int U, int VV, const SpmvArgs &a, hipStream_t s
     hipLaunchKernelGGL((k_combine<COMBO, CC>), dim3(nbc), dim3(64 * kWavesPerBlock), 0, s, a);               \
     return hipGetLastError();                                                                                \
   }
-  SELL_FOR_EACH_CUV(SELL_L)
+  if constexpr (ZS == 2) {
+    SELL_FOR_EACH_CUV_RL(SELL_L)
+  } else {
+    SELL_FOR_EACH_CUV(SELL_L)
+  }
 #undef SELL_L
   return hipErrorInvalidValue;
 }
 
 template <int COMBO>
 hipError_t launch_spmv_t(int C, int U, int VV, bool skip_zero, const SpmvArgs &a, hipStream_t s) {
-  return skip_zero ? launch_spmv_zs<COMBO, true>(C, U, VV, a, s) : launch_spmv_zs<COMBO, false>(C, U, VV, a, s);
+  if (a.rl) return launch_spmv_zs<COMBO, 2>(C, U, VV, a, s);
+  return skip_zero ? launch_spmv_zs<COMBO, 1>(C, U, VV, a, s) : launch_spmv_zs<COMBO, 0>(C, U, VV, a, s);
 }
 
 // C in {8, 16, 32, 64}; V slots per lane (1, 2, or 4 for FP32/BF16 values,

@@ -42,7 +42,8 @@ class SellAllocator(ctypes.Structure):
 class SellBuildOpts(ctypes.Structure):
     _fields_ = [("val_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int), ("unroll", c_i32), ("vec", c_i32),
                 ("seg_cols", c_i32), ("ktile", c_i32), ("kmax", c_i32), ("permute_columns", c_i32),
-                ("xwindow", c_i32), ("alloc", ctypes.POINTER(SellAllocator)), ("xwindow_chunks", c_i32)]
+                ("xwindow", c_i32), ("alloc", ctypes.POINTER(SellAllocator)), ("xwindow_chunks", c_i32),
+                ("row_lengths", c_i32)]
 
 
 class SellInfo(ctypes.Structure):
@@ -51,7 +52,8 @@ class SellInfo(ctypes.Structure):
                 ("val_dtype", ctypes.c_int), ("x_dtype", ctypes.c_int), ("acc_dtype", ctypes.c_int),
                 ("lanes_per_row", c_i32), ("unroll", c_i32), ("vec", c_i32), ("seg_cols", c_i32), ("nunits", c_i64),
                 ("nsplit", c_i64), ("has_perm", c_i32), ("permuted_columns", c_i32), ("device_bytes", c_i64),
-                ("xwindow", c_i32), ("xwindow_max", c_i32), ("xsegments", c_i64), ("xwindow_group_chunks", c_i32)]
+                ("xwindow", c_i32), ("xwindow_max", c_i32), ("xsegments", c_i64), ("xwindow_group_chunks", c_i32),
+                ("row_lengths", c_i32)]
 
 
 class SellTuneSpace(ctypes.Structure):
@@ -253,10 +255,12 @@ class SellMatrix:
 def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "f64", acc_dtype: str | None = None,
                unroll: int = 0, vec: int = 0, seg_cols: int = 0, ktile: int = 0, kmax: int = 0,
                permute_columns: bool = False, xwindow: int = 0, allocator: TorchAllocator | None = None,
-               stream=None, xwindow_chunks: int = 0) -> SellMatrix:
+               stream=None, xwindow_chunks: int = 0, row_lengths: bool = False) -> SellMatrix:
     """Build SELL-C-sigma from device CRS tensors (rpt int64, col int32, val float64).
     xwindow: 0 stage x windows in LDS when they fit, -1 never, 1 required.
     xwindow_chunks: chunks per window group, 0 auto (8 at C = 32 when they fit), 4 or 8.
+    row_lengths: keep every row's length; sell_spmv's lanes then stop at
+    their rows' ends (global-index product, C in 8..64; same result bit for bit).
     allocator: a TorchAllocator to take the handle's device memory from
     torch's caching allocator (default: the library's hipMalloc)."""
     import torch
@@ -268,7 +272,8 @@ def sell_build(rpt, col, val, ncols: int, C: int, sigma: int, val_dtype: str = "
         acc_dtype = "f64" if val_dtype == "f64" else "f32"
     o = SellBuildOpts(DTYPES[val_dtype], DTYPES[acc_dtype], unroll, vec, seg_cols, ktile, kmax,
                       1 if permute_columns else 0, xwindow,
-                      ctypes.pointer(allocator.struct) if allocator else None, xwindow_chunks)
+                      ctypes.pointer(allocator.struct) if allocator else None, xwindow_chunks,
+                      1 if row_lengths else 0)
     h = c_p()
     _check(lib().sell_build(ctypes.byref(A), C, sigma, ctypes.byref(o), _stream(stream), ctypes.byref(h)), "sell_build")
     return SellMatrix(h, allocator)

@@ -87,6 +87,14 @@ def test_host_side_argument_errors(L):
         badg = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, xwindow_chunks=g)
         assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badg), None,
                             ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    for r in (-1, 2):
+        badr = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, row_lengths=r)
+        assert L.sell_build(ctypes.byref(A), 32, 1, ctypes.byref(badr), None,
+                            ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
+    for C in (1, 4, 128):  # row lengths are kept for C in 8..64 only
+        rl = sellcs.SellBuildOpts(val_dtype=0, acc_dtype=0, row_lengths=1)
+        assert L.sell_build(ctypes.byref(A), C, 1, ctypes.byref(rl), None,
+                            ctypes.byref(h)) == sellcs.SELL_ERR_UNSUPPORTED
     assert L.sell_spmv(None, None, None, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_spmmv(None, None, None, 4, None) == sellcs.SELL_ERR_INVALID_ARG
     assert L.sell_batch_create(None, 0, ctypes.byref(h)) == sellcs.SELL_ERR_INVALID_ARG
