@@ -524,7 +524,8 @@ def sigma_sweep(args):
     """SELL-32-sigma on the power-law n = 2,000,000 matrix for sigma = 1 ..
     n: beta, time and GF/s per sigma (the analog of the paper's sigma study of
     kkt_power, Sect. 5.3). Under a counter run (--pmc-pass) each sigma runs
-    exactly 3 products so the dispatches can be attributed."""
+    exactly 3 products so the dispatches can be attributed. --row-lengths:
+    the same with the lanes stopped at their rows' ends."""
     import torch
     import synth
     from paper_1307_6209_amd import sellcs
@@ -534,7 +535,7 @@ def sigma_sweep(args):
     y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
     rows = []
     for sg in SWEEP_SIGMAS:
-        h = sellcs.sell_build(r, c, v, A.ncols, 32, sg)
+        h = sellcs.sell_build(r, c, v, A.ncols, 32, sg, row_lengths=args.row_lengths)
         if args.pmc_pass:
             for _ in range(3):
                 sellcs.sell_spmv(h, x, y)
@@ -549,7 +550,8 @@ def sigma_sweep(args):
     if args.pmc_pass:
         sellcs.sell_probe_bandwidth(1, 1 << 30, 1)
         torch.cuda.synchronize()
-    print(json.dumps({"sigma_sweep": "powerlaw_2m", "C": 32, "n": A.nrows, "nnz": A.nnz, "rows": rows}))
+    print(json.dumps({"sigma_sweep": "powerlaw_2m", "C": 32, "n": A.nrows, "nnz": A.nnz,
+                      "row_lengths": bool(args.row_lengths), "rows": rows}))
 
 
 def block_pass(args):
@@ -638,6 +640,8 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true",
                     help="short run for hardware counters: a few products and one copy probe")
     ap.add_argument("--sigma-sweep", action="store_true", help="SELL-32-sigma sweep on the power-law matrix")
+    ap.add_argument("--row-lengths", action="store_true",
+                    help="with --sigma-sweep: lanes stopped at their rows' ends (build option row_lengths)")
     ap.add_argument("--block-pass", action="store_true",
                     help="block form k = 16, 32, 64 on the power-law 1M matrix (with --pmc-pass: for counters)")
     ap.add_argument("--batch-pass", action="store_true",
