@@ -370,6 +370,10 @@ typedef struct {
   const int32_t *xwindow_chunks; int32_t nxwindow_chunks; /* waves per workgroup of the window
                                                product: the xwindow_chunks build option
                                                (0 = automatic, 4, 8); NULL/0: {0} */
+  const int32_t *row_lengths; int32_t nrow_lengths; /* the row_lengths build option (0, 1);
+                                               1 is skipped for C outside 8..64 and where
+                                               the layout runs the x-window product;
+                                               NULL/0: {0} */
 } sell_tune_space;
 
 typedef struct {
@@ -386,6 +390,7 @@ typedef struct {
   int32_t predicted;    /* configurations ranked by the model (model_guided > 0) */
   int32_t xwindow;      /* 1 when the fastest product staged x windows in LDS */
   int32_t xwindow_chunks; /* its chunks (waves) per window workgroup; 0 without window */
+  int32_t row_lengths;  /* 1 when the fastest product stopped its lanes at their rows' ends */
 } sell_tuned;
 
 /*

@@ -1167,6 +1167,8 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   int nX = sp.nxwindow > 0 ? sp.nxwindow : 1;
   const int32_t *Ws = sp.nxwindow_chunks > 0 ? sp.xwindow_chunks : defX;
   int nW = sp.nxwindow_chunks > 0 ? sp.nxwindow_chunks : 1;
+  const int32_t *Rs = sp.nrow_lengths > 0 ? sp.row_lengths : defX;
+  int nR = sp.nrow_lengths > 0 ? sp.nrow_lengths : 1;
   sell_build_opts o{};
   o.val_dtype = sp.val_dtype;
   o.acc_dtype = sp.acc_dtype;
@@ -1220,21 +1222,29 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
   r.gflops = -1.0;
   int cands = 0;
   for (const auto &cand : order) {
-    for (int iv = 0; iv < nV * nG * nX * nW; ++iv) {
+    for (int iv = 0; iv < nV * nG * nX * nW * nR; ++iv) {
       const int ic = cand.first, is = cand.second;
-      // slots per lane, split width, x path and window workgroup size are
-      // build parameters: one build each
+      // slots per lane, split width, x path, window workgroup size and row
+      // lengths are build parameters: one build each
       o.vec = Vs[iv % nV];
       o.seg_cols = Gs[(iv / nV) % nG];
       o.xwindow = Xs[(iv / (nV * nG)) % nX];
-      o.xwindow_chunks = Ws[iv / (nV * nG * nX)];
+      o.xwindow_chunks = Ws[(iv / (nV * nG * nX)) % nW];
+      o.row_lengths = Rs[iv / (nV * nG * nX * nW)];
+      // row lengths need C in 8..64 and serve the single-vector product only
+      if (o.row_lengths && (Cs[ic] < 8 || Cs[ic] > 64 || k > 1)) continue;
       sell_handle h = nullptr;
       sell_status st = sell_build(A, Cs[ic], Ss[is], &o, stream, &h);
       if (st == SELL_ERR_UNSUPPORTED || st == SELL_ERR_INVALID_ARG) continue;
       if (st != SELL_OK) return st;
       // without a window the size does not change the product: time it for
       // the first size of the list only
-      if (!h->lcol && iv / (nV * nG * nX) > 0) {
+      if (!h->lcol && (iv / (nV * nG * nX)) % nW > 0) {
+        sell_destroy(h);
+        continue;
+      }
+      // the window product does not read the row lengths: nothing to time
+      if (h->lcol && h->rl) {
         sell_destroy(h);
         continue;
       }
@@ -1270,6 +1280,7 @@ extern "C" sell_status sell_autotune(const sell_crs *A, int32_t k, const sell_tu
             r.ktile = h->ktile;
             r.xwindow = h->lcol ? 1 : 0;
             r.xwindow_chunks = h->lcol ? h->xw_gc : 0;
+            r.row_lengths = h->rl ? 1 : 0;
             r.gflops = gf;
             r.us_per_call = t * 1e6;
             r.beta = h->beta;

@@ -63,14 +63,15 @@ class SellTuneSpace(ctypes.Structure):
                 ("seg_cols", ctypes.POINTER(c_i32)), ("nseg_cols", c_i32), ("val_dtype", ctypes.c_int),
                 ("acc_dtype", ctypes.c_int), ("reps", c_i32), ("model_guided", c_i32),
                 ("xwindow", ctypes.POINTER(c_i32)), ("nxwindow", c_i32),
-                ("xwindow_chunks", ctypes.POINTER(c_i32)), ("nxwindow_chunks", c_i32)]
+                ("xwindow_chunks", ctypes.POINTER(c_i32)), ("nxwindow_chunks", c_i32),
+                ("row_lengths", ctypes.POINTER(c_i32)), ("nrow_lengths", c_i32)]
 
 
 class SellTuned(ctypes.Structure):
     _fields_ = [("C", c_i32), ("sigma", c_i64), ("unroll", c_i32), ("ktile", c_i32), ("vec", c_i32),
                 ("seg_cols", c_i32), ("gflops", c_d),
                 ("us_per_call", c_d), ("beta", c_d), ("candidates", c_i32), ("predicted", c_i32),
-                ("xwindow", c_i32), ("xwindow_chunks", c_i32)]
+                ("xwindow", c_i32), ("xwindow_chunks", c_i32), ("row_lengths", c_i32)]
 
 
 class SellBatchTuned(ctypes.Structure):
@@ -449,9 +450,10 @@ def sell_batch_destroy(b: SellBatch):
 
 def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=(), ktile=(), vec=(), seg_cols=(),
                   val_dtype: str = "f64", acc_dtype: str | None = None, reps: int = 0, model_guided: int = 0,
-                  xwindow=(), stream=None, xwindow_chunks=()) -> dict:
+                  xwindow=(), stream=None, xwindow_chunks=(), row_lengths=()) -> dict:
     """Time the configurations of the search space (all of them, or the
-    model_guided best by the code-balance model); return the fastest."""
+    model_guided best by the code-balance model); return the fastest.
+    row_lengths: values of the row_lengths build option to try (0, 1)."""
     import torch
     nrows = rpt.numel() - 1
     nnz = col.numel()
@@ -463,9 +465,10 @@ def sell_autotune(rpt, col, val, ncols: int, k: int = 1, C=(), sigma=(), unroll=
             (c_i32 * len(ktile))(*ktile), (c_i32 * len(vec))(*vec), (c_i32 * len(seg_cols))(*seg_cols)]
     xa = (c_i32 * len(xwindow))(*xwindow)
     wa = (c_i32 * len(xwindow_chunks))(*xwindow_chunks)
+    ra = (c_i32 * len(row_lengths))(*[int(v) for v in row_lengths])
     sp = SellTuneSpace(arrs[0], len(C), arrs[1], len(sigma), arrs[2], len(unroll), arrs[3], len(ktile),
                        arrs[4], len(vec), arrs[5], len(seg_cols), DTYPES[val_dtype], DTYPES[acc_dtype], reps,
-                       model_guided, xa, len(xwindow), wa, len(xwindow_chunks))
+                       model_guided, xa, len(xwindow), wa, len(xwindow_chunks), ra, len(row_lengths))
     r = SellTuned()
     _check(lib().sell_autotune(ctypes.byref(A), k, ctypes.byref(sp), _stream(stream), ctypes.byref(r)), "sell_autotune")
     return {name: getattr(r, name) for name, _ in SellTuned._fields_}

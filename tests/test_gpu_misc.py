@@ -2,7 +2,7 @@
 import pytest
 
 import synth
-from gpu_util import dev_crs, say
+from gpu_util import build, check_fp64, dev_crs, say, spmv_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -156,3 +156,26 @@ def test_autotune_window_workgroup_size():
     say("autotune window workgroup size", r)
     assert r["candidates"] == 3
     assert (r["xwindow"], r["xwindow_chunks"]) in ((0, 0), (1, 4), (1, 8))
+
+
+def test_autotune_row_lengths():
+    """The row_lengths build option is searched too: both values timed where
+    they apply (C in 8..64, single vector, no x window), the option skipped
+    elsewhere; the winner, rebuilt as reported, gives the oracle's product."""
+    from paper_1307_6209_amd import sellcs
+    A = synth.powerlaw(60_000, seed=31)
+    rpt, col, val = dev_crs(A)
+    r = sellcs.sell_autotune(rpt, col, val, A.ncols, k=1, C=(4, 32), sigma=(1024,), unroll=(8,), xwindow=(-1,),
+                             row_lengths=(0, 1), reps=10)
+    say("autotune row lengths", r)
+    assert r["candidates"] == 3  # C = 4 without row lengths only
+    assert r["row_lengths"] in (0, 1) and (r["row_lengths"] == 0 or r["C"] == 32)
+    h = build(A, r["C"], r["sigma"], unroll=r["unroll"], vec=r["vec"], xwindow=-1, row_lengths=bool(r["row_lengths"]))
+    x = synth.uniform(A.ncols, 31, 1)
+    check_fp64(A, spmv_gpu(h, x), x)
+    # a window layout does not time the row-length product
+    S = synth.stencil27(64)
+    rs, cs_, vs = dev_crs(S)
+    r2 = sellcs.sell_autotune(rs, cs_, vs, S.ncols, k=1, C=(32,), sigma=(1,), unroll=(8,), xwindow=(1,),
+                              row_lengths=(0, 1), reps=10)
+    assert r2["candidates"] == 1 and r2["row_lengths"] == 0 and r2["xwindow"] == 1
